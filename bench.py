@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the LiFE hot path on one MI355X.
+
+A step is one SBB-NNLS iteration (Algorithm 1) through the C ABI: two DSC
+(y = M w), one or two WC (g = M^T y; two on even iterations) and the step
+glue, on the synthetic full-scale connectome (N_theta = 96, N_a = 1057,
+~300k voxels, 1.5M fascicles, ~90M nonzeros) with every input resident in HBM.
+The plan (restructuring) is built once before the timed region.
+
+Output: one JSON line.  ``value`` = Phi nonzeros per second per DSC+WC pair:
+nnz * (DSC calls + WC calls) / 2 / wall time of the K timed iterations (glue
+included).  ``roofline`` covers the kernel with the largest share of the time,
+from HIP events recorded around every launch of the timed region on the
+launch stream; ``cpu_baseline`` times the FP64 oracle (DSC + WC) on a bounded
+random sample of the same nonzeros.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU * 4 SIMD * 16 lanes * 2 flop * 2.4 GHz (unpacked FP32 FMA)
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic(kind: str, d) -> tuple[float, float]:
+    """(bytes, flops) the method must move / compute per launch of a kernel class."""
+    nnz, nt, nv, nf, na = d.nnz, d.n_theta, d.n_voxels, d.n_fascicles, d.n_atoms
+    if kind == "dsc":      # sorted (atom, fascicle, phi) streams, w gathered once, y written once, D once
+        return 10.0 * nnz + 4.0 * nt * nv + 4.0 * nf + 4.0 * nt * na + 4.0 * (nv + 1), (2.0 * nt + 1) * nnz
+    if kind == "wc_z":     # (atom, phi) streams, y read once, D once, one z per nonzero written
+        return 10.0 * nnz + 4.0 * nt * nv + 4.0 * nt * na + 4.0 * (nv + 1), (2.0 * nt + 1) * nnz
+    if kind == "wc_sum":   # permutation and z read, g written
+        return 8.0 * nnz + 4.0 * nf + 4.0 * (nf + 1), 1.0 * nnz
+    return 0.0, 0.0
+
+
+def cpu_baseline(c, target_s: float):
+    """FP64 oracle DSC + WC on a random sample of the nonzeros (bounded time)."""
+    import numpy as np
+    import oracle
+
+    def run(n):
+        op = oracle.Operator(c.atom[:n], c.voxel[:n], c.fascicle[:n], c.phi[:n], c.D, c.n_voxels, c.n_fascicles)
+        w = c.w0.astype(np.float64)
+        y = c.noise.astype(np.float64)
+        t0 = time.perf_counter()
+        op.dsc(w)
+        t1 = time.perf_counter()
+        op.wc(y)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    probe = min(c.nnz, 1_000_000)
+    a, b = run(probe)
+    n = int(min(c.nnz, max(probe, probe * target_s / max(a + b, 1e-9))))
+    t_dsc, t_wc = run(n) if n != probe else (a, b)
+    return {"value": n / (t_dsc + t_wc), "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {c.nnz} nonzeros (input order is a seeded random permutation); "
+                      f"one DSC ({t_dsc:.2f} s) + one WC ({t_wc:.2f} s), sequential C, float64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--config", default="full", choices=["tiny", "mid", "full"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the voxel-sharded design is described, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_06234_amd import life
+
+    life.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    c = synth.make(args.config)
+    log(f"generated {args.config}: nnz={c.nnz} Nv={c.n_voxels} Nf={c.n_fascicles} ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    plan = life.Plan.from_connectome(c)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    log(f"plan built in {plan_ms:.0f} ms")
+    d = plan.dims
+
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    w = torch.from_numpy(c.w0).to(dev)
+    # b = M w_true + 5% noise, formed with the library's own DSC (input preparation)
+    y_true = plan.dsc(D, torch.from_numpy(c.w_true).to(dev))
+    rms = torch.sqrt(torch.mean(y_true.double() ** 2)).float()
+    b = y_true + 0.05 * rms * torch.from_numpy(c.noise).to(dev)
+    del y_true
+    state = life.new_state(dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        plan.sbbnnls_step(D, b, w, state)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    plan.profile_read()                 # drop anything recorded so far
+    plan.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.sbbnnls_step(D, b, w, state)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.profile_enable(False)
+    ms, cnt = plan.profile_read()
+    st = life.read_state(state)
+    log(f"timed {args.steps} steps: {wall * 1e3:.2f} ms; kernel ms {ms}; f={st['obj']:.6e} alpha={st['alpha']:.3e}")
+
+    n_dsc = cnt["dsc"]
+    n_wc = cnt["wc_sum"]
+    pairs = (n_dsc + n_wc) / 2.0
+    value = d.nnz * pairs / wall
+    avg = {k: (ms[k] / cnt[k] if cnt[k] else 0.0) for k in ms}
+    t_dsc = avg["dsc"]
+    t_wc = avg["wc_z"] + avg["wc_sum"]
+
+    dom = max(("dsc", "wc_z", "wc_sum"), key=lambda k: ms[k])
+    by, fl = algorithmic(dom, d)
+    t_s = avg[dom] / 1e3
+    bw = by / t_s / 1e9
+    tf = fl / t_s / 1e12
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    t_alu = fl / (FP32_FMA_PEAK_TFLOPS * 1e12)
+    if t_alu > t_hbm:
+        roof = {"bound": "alu", "achieved": round(tf, 3), "peak": FP32_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP32_FMA_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(bw / HBM_PEAK_GBS, 4)}
+    roof.update({"traffic": None, "kernel": dom, "avg_ms": round(avg[dom], 4),
+                 "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
+                 "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})
+
+    out = {
+        "metric": "Phi nonzeros/s for DSC (Mw)+WC (M^T y) per SBB-NNLS iteration; % HBM peak",
+        "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.config} synthetic connectome", "n_theta": d.n_theta, "n_atoms": d.n_atoms,
+                   "n_voxels": d.n_voxels, "n_fascicles": d.n_fascicles, "nnz": d.nnz,
+                   "step": "one SBB-NNLS iteration (2 DSC + 1 or 2 WC + glue)"},
+        "pair_kernel_nnz_per_s": round(d.nnz / ((t_dsc + t_wc) / 1e3), 1) if t_dsc + t_wc > 0 else None,
+        "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},
+        "kernel_launches": cnt,
+        "plan_ms": round(plan_ms, 1),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample ...")
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * life.h - C ABI of the MI355X (gfx950) library for the hot path of the Linear
+ * Fascicle Evaluation (LiFE) method: the two sparse-Tucker-decomposed products
+ * that every SBB-NNLS iteration runs, and the iteration itself.
+ *
+ * Source: Aggarwal & Bondhugula, "Optimizing the Linear Fascicle Evaluation
+ * Algorithm for Multi-Core and Many-Core Systems" (arxiv 1905.06234).
+ *
+ * Model.  The diffusion signal y (N_theta*N_v values) is approximated by M w
+ * (Sec. 2.1, eq. 1), with M never formed: for each voxel v, M_v = D Phi_v
+ * (eq. 3, with the S0(v) factor folded into the Phi values), i.e. the tensor
+ * form Y = Phi x1 D x2 S0 x3 w^T (eq. 4).  Phi is given as one
+ * (atom, voxel, fascicle, value) entry per nonzero (Sec. 2.2: the atoms,
+ * voxels, fibers and values vectors).
+ *
+ * Conventions for every call:
+ *   - Indices are 0-based.  atom is int16, voxel and fascicle are int32.
+ *   - D is N_theta x N_a, stored theta-fastest: D[t + N_theta*a] (the offset
+ *     rule "N_theta times the index" of Sec. 4.1).  Signals (y, b, r) are
+ *     stored theta-fastest per voxel: y[t + N_theta*v].
+ *   - Floating point data are IEEE float32; scalar reductions inside
+ *     life_sbbnnls_step are carried in float64.
+ *   - "device" pointers are HIP device memory on the device the plan was built
+ *     on; "host" pointers are ordinary host memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     life_dsc, life_wc and life_sbbnnls_step only enqueue work: they never
+ *     allocate, free or synchronize.
+ *   - Results are deterministic: the same plan and inputs give bitwise equal
+ *     outputs on every call (fixed reduction orders, no atomics).
+ *   - A plan owns a workspace; calls that share one plan must not overlap in
+ *     time (enqueue them on one stream, or order the streams).
+ *   - Every function returns a life_status; on an error nothing is enqueued
+ *     and outputs are left untouched unless stated.
+ */
+#ifndef LIFE_H
+#define LIFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LIFE_OK = 0,
+    LIFE_EINVAL = 1,  /* NULL pointer, negative size, dimension out of its limits */
+    LIFE_ERANGE = 2,  /* an index outside [0, n), or nnz beyond 2^31 - 2 */
+    LIFE_ENOMEM = 3,  /* host or device allocation failed */
+    LIFE_EDEVICE = 4  /* HIP runtime error (no device, wrong device, launch failure) */
+} life_status;
+
+/* Problem dimensions.  Limits: 1 <= n_theta <= 1024; 1 <= n_atoms <= 32767;
+ * n_voxels, n_fascicles >= 0; 0 <= nnz <= 2^31 - 2.  nnz = 0 is legal (M = 0). */
+typedef struct {
+    int32_t n_theta;      /* N_theta: diffusion directions (rows of D)          */
+    int32_t n_atoms;      /* N_a: dictionary atoms (columns of D)                 */
+    int32_t n_voxels;     /* N_v                                                  */
+    int32_t n_fascicles;  /* N_f: length of w                                     */
+    int64_t nnz;          /* N_c: nonzeros of Phi                                 */
+} life_dims;
+
+/* Opaque plan: the restructured (sorted) copies of Phi on one device, plus the
+ * workspace of the calls below. */
+typedef struct life_plan_s *life_plan_t;
+
+/* Device-resident state of SBB-NNLS (Algorithm 1), written by
+ * life_sbbnnls_step.  Zero it (all bytes) to start at iteration 0; to resume,
+ * keep w and set iter. */
+typedef struct {
+    int64_t iter;      /* i: the next iteration to run (counted from 0)                */
+    double alpha;      /* alpha^(i) used by the last completed iteration               */
+    double obj;        /* f(w^(i)) = 1/2 ||M w^(i) - b||^2 (eq. 2) at that iteration   */
+    double gt_norm2;   /* ||g~||^2 of the projected gradient at that iteration         */
+    double num;        /* numerator of that alpha                                      */
+    double den;        /* denominator of that alpha (0 -> alpha = 0, w unchanged)      */
+} life_sbb_state;
+
+/* Kernel classes reported by the profiling hooks. */
+typedef enum {
+    LIFE_K_DSC = 0,        /* y = M w (voxel-segmented)                          */
+    LIFE_K_WC_Z = 1,       /* WC pass 1: per-nonzero projections, voxel order     */
+    LIFE_K_WC_SUM = 2,     /* WC pass 2: per-fascicle sums                        */
+    LIFE_K_MASK = 3,       /* projected gradient g~ and ||g~||^2 partials          */
+    LIFE_K_ALPHA = 4,      /* step length from the partial sums                   */
+    LIFE_K_UPDATE = 5,     /* w <- [w - alpha g~]_+                               */
+    LIFE_K_COUNT = 6
+} life_kernel_kind;
+
+/* Human-readable name of a status code (static string; never NULL). */
+const char *life_status_str(life_status s);
+
+/* Restructuring on the host only (no device touched): the data-restructuring
+ * step of Sec. 4.1 ("Data Restructuring": voxel-based for DSC; fiber-based,
+ * i.e. by fascicle, for WC) as two permutations with their segment offsets.
+ *   atom, voxel, fascicle: host, nnz entries each (input COO order).
+ *   dsc_perm  (host, nnz):          input positions in DSC order, the total order
+ *                                   (voxel, atom, fascicle, input position).
+ *   vox_ptr   (host, n_voxels+1):   voxel v owns DSC positions [vox_ptr[v], vox_ptr[v+1]).
+ *   wc_perm   (host, nnz):          for WC slot j, its position in the DSC order; WC
+ *                                   slots follow (fascicle, voxel, atom, input position).
+ *   fas_ptr   (host, n_fascicles+1): fascicle f owns WC slots [fas_ptr[f], fas_ptr[f+1]).
+ * Any output may be NULL (not written).  Errors: LIFE_EINVAL (dims or a needed
+ * pointer NULL), LIFE_ERANGE (an index out of range), LIFE_ENOMEM. */
+life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                           const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
+                           int32_t *wc_perm, int32_t *fas_ptr);
+
+/* Build a plan on the current HIP device from host COO arrays (Sec. 2.2 Phi
+ * vectors; restructuring of Sec. 4.1 done once and amortized over the
+ * iterations, as the paper does before SBB-NNLS).  Copies the sorted arrays to
+ * the device and allocates the workspace.  Synchronous.  The inputs are not
+ * retained.  On success *out owns device memory until life_plan_destroy.
+ * Errors: LIFE_EINVAL, LIFE_ERANGE (index checks happen here, once),
+ * LIFE_ENOMEM, LIFE_EDEVICE. */
+life_status life_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                      const int32_t *fascicle, const float *phi, life_plan_t *out);
+
+/* Release a plan and its device memory (synchronizes the device first).
+ * NULL is accepted and ignored. */
+life_status life_plan_destroy(life_plan_t plan);
+
+/* Dimensions the plan was built with (host output). */
+life_status life_plan_dims(life_plan_t plan, life_dims *out);
+
+/* Copy the plan's device arrays to host buffers (any may be NULL): the DSC
+ * order arrays vox_ptr (n_voxels+1), atom_v, fas_v, phi_v (nnz each), and the
+ * WC order arrays fas_ptr (n_fascicles+1) and wc_perm (nnz).  Synchronous. */
+life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v, int32_t *fas_v,
+                             float *phi_v, int32_t *fas_ptr, int32_t *wc_perm);
+
+/* DSC, the diffusion signal computation y = M w (eq. 1; Sec. 2.2, the "daxpy"
+ * form of the inner loop): y[t + N_theta*v] = sum over nonzeros c of voxel v of
+ * D[t + N_theta*atom_c] * phi_c * w[fascicle_c].
+ *   D (device, N_theta*N_a), w (device, N_f) are read; y (device, N_theta*N_v) is
+ *   overwritten (voxels with no nonzero get 0).  Nonzeros whose phi_c*w[f_c] is
+ *   zero are skipped (the paper's use of the sparsity of w).
+ * Errors: LIFE_EINVAL (NULL plan or pointer with a nonzero size), LIFE_EDEVICE. */
+life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream);
+
+/* WC, the weight computation g = M^T y (the transpose product of eq. 6; Sec. 2.2,
+ * the "dot-product" form): g[f] = sum over nonzeros c of fascicle f of
+ * phi_c * sum_t D[t + N_theta*atom_c] * y[t + N_theta*voxel_c].
+ *   D (device), y (device, N_theta*N_v) are read; g (device, N_f) is
+ *   overwritten (fascicles with no nonzero get 0).
+ * Errors: as life_dsc. */
+life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream);
+
+/* One SBB-NNLS iteration, Algorithm 1 (Sec. 2.1) with eqs. 5-6:
+ *   r  = M w - b;   g = M^T r  (the gradient, eq. 6);
+ *   g~ = g with g_f set to 0 where w_f = 0 and g_f > 0 (projected gradient);
+ *   v' = M g~;
+ *   i odd : alpha = <g~,g~> / <v',v'>;
+ *   i even: v'' = M^T v';  alpha = <v',v'> / <v'',v''>;
+ *   (a zero denominator gives alpha = 0)
+ *   w <- [w - alpha g~]_+  (eq. 5; non-positive results become +0).
+ * i is state->iter; the call increments it and records alpha, f(w), ||g~||^2,
+ * numerator and denominator in *state.  Two DSC and, on even i, two WC (one WC
+ * on odd i) run per call: on average 2 and 1.5, as the paper counts.
+ *   D (device), b (device, N_theta*N_v) are read; w (device, N_f) is updated in
+ *   place; state (device) is read and written.  Everything stays on the device.
+ * Errors: as life_dsc. */
+life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
+                              life_sbb_state *state, void *stream);
+
+/* Profiling hooks for the benchmark: when enabled, every kernel the plan
+ * launches is bracketed by HIP events on its stream.  life_profile_read
+ * synchronizes those events, writes per-kind total milliseconds and launch
+ * counts (arrays of LIFE_K_COUNT entries, host; either may be NULL) and
+ * resets the record. */
+life_status life_profile_enable(life_plan_t plan, int enable);
+life_status life_profile_read(life_plan_t plan, double *ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIFE_H */

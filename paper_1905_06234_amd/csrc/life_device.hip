@@ -1,0 +1,621 @@
+// HIP (gfx950) kernels and the C ABI of the LiFE sparse-Tucker products.
+//
+// DSC  y = M w   (eq. 1, M_v = D Phi_v of eq. 3): a voxel-segmented reduction
+//      over the voxel-sorted nonzeros.  32 lanes own one voxel; lane l holds
+//      the accumulators y[l + 32k] of that voxel in registers for the whole
+//      segment, so y is written exactly once and no atomics are needed.
+// WC   g = M^T y  (the transpose product of eq. 6), in two deterministic passes:
+//      (1) voxel-major: the voxel's signal column stays in registers while each
+//          of its nonzeros c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
+//      (2) fascicle-major: g[f] = sum of z over the fascicle's nonzeros, read
+//          through the fascicle-sorted permutation, in a fixed tree order.
+// SBB  one SBB-NNLS iteration (Algorithm 1) chains these with a mask kernel, a
+//      one-block step-length kernel and an update kernel; every scalar stays on
+//      the device and every reduction has a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "life_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;                  // threads per block (4 wave64)
+constexpr int kSeg = 32;                     // lanes per voxel segment
+constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block
+constexpr int kFasLanes = 16;                // lanes per fascicle in the WC sum
+constexpr int kFasPerBlock = kBlock / kFasLanes;
+
+// ----------------------------------------------------------------------------- device helpers
+
+// Sum a double over the block in a fixed order and store it at out[blockIdx.x].
+__device__ __forceinline__ void block_sum_store(double v, double *out)
+{
+    __shared__ double sh[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+        out[blockIdx.x] = s;
+    }
+}
+
+// Fixed-order sum of n doubles by one block; the result is valid in thread 0.
+__device__ double block_sum_array(const double *a, int n)
+{
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += a[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ----------------------------------------------------------------------------- DSC
+
+// y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
+// NT = accumulator slots per lane: lane l covers theta = l + 32 t, t < NT.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_dsc(const int32_t *__restrict__ vptr,
+                                                 const int16_t *__restrict__ atom,
+                                                 const int32_t *__restrict__ fas,
+                                                 const float *__restrict__ phi,
+                                                 const float *__restrict__ w,
+                                                 const float *__restrict__ D,
+                                                 const float *__restrict__ bsub,
+                                                 float *__restrict__ y, double *__restrict__ part,
+                                                 int nth, int nv)
+{
+    const int lane = threadIdx.x & (kSeg - 1);
+    const int v = blockIdx.x * kSegPerBlock + (threadIdx.x / kSeg);
+    float acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.f;
+    if (v < nv) {
+        const int beg = vptr[v], end = vptr[v + 1];
+        for (int base = beg; base < end; base += kSeg) {
+            const int j = base + lane;
+            int a = 0;
+            float s = 0.f;
+            if (j < end) {
+                a = atom[j];
+                s = phi[j] * w[fas[j]];     // loop-invariant product hoisted (Sec. 4.1)
+            }
+            const int cnt = min(kSeg, end - base);
+            for (int k = 0; k < cnt; ++k) {
+                const float sk = __shfl(s, k, kSeg);
+                const int ak = __shfl(a, k, kSeg);
+                if (sk != 0.f) {            // zero weights contribute nothing
+                    const float *__restrict__ d = D + (size_t)ak * nth + lane;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        if (lane + kSeg * t < nth) acc[t] = fmaf(d[kSeg * t], sk, acc[t]);
+                }
+            }
+        }
+    }
+    double sq = 0.0;
+    if (v < nv) {
+        float *yv = y + (size_t)v * nth;
+        const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int th = lane + kSeg * t;
+            if (th < nth) {
+                float r = acc[t];
+                if (bv) r -= bv[th];
+                yv[th] = r;
+                sq += (double)r * (double)r;
+            }
+        }
+    }
+    if (part) block_sum_store(sq, part);
+}
+
+// ----------------------------------------------------------------------------- WC
+
+// Pass 1: z[c] = phi_c * <D[:, atom_c], y[:, v]> for every nonzero c, voxel order.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vptr,
+                                                  const int16_t *__restrict__ atom,
+                                                  const float *__restrict__ phi,
+                                                  const float *__restrict__ D,
+                                                  const float *__restrict__ y,
+                                                  float *__restrict__ z, int nth, int nv,
+                                                  const life_sbb_state *__restrict__ gate)
+{
+    if (gate && (gate->iter & 1)) return;   // this launch belongs to even iterations only
+    const int lane = threadIdx.x & (kSeg - 1);
+    const int v = blockIdx.x * kSegPerBlock + (threadIdx.x / kSeg);
+    if (v >= nv) return;
+    float yv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int th = lane + kSeg * t;
+        yv[t] = th < nth ? y[(size_t)v * nth + th] : 0.f;
+    }
+    const int beg = vptr[v], end = vptr[v + 1];
+    for (int base = beg; base < end; base += kSeg) {
+        const int j = base + lane;
+        int a = 0;
+        float p = 0.f;
+        if (j < end) {
+            a = atom[j];
+            p = phi[j];
+        }
+        const int cnt = min(kSeg, end - base);
+        float mine = 0.f;
+        for (int k = 0; k < cnt; ++k) {
+            const int ak = __shfl(a, k, kSeg);
+            const float *__restrict__ d = D + (size_t)ak * nth + lane;
+            float q = 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                if (lane + kSeg * t < nth) q = fmaf(d[kSeg * t], yv[t], q);
+#pragma unroll
+            for (int o = kSeg / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, kSeg);
+            if (lane == k) mine = q;
+        }
+        if (j < end) z[j] = p * mine;
+    }
+}
+
+// Pass 2: g[f] = sum_{j in seg(f)} z[wperm[j]]  (16 lanes per fascicle, fixed tree).
+__global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
+                                                    const int32_t *__restrict__ wperm,
+                                                    const float *__restrict__ z,
+                                                    float *__restrict__ g, double *__restrict__ part,
+                                                    int nf, const life_sbb_state *__restrict__ gate)
+{
+    if (gate && (gate->iter & 1)) return;   // uniform over the grid
+    const int lane = threadIdx.x & (kFasLanes - 1);
+    const int f = blockIdx.x * kFasPerBlock + threadIdx.x / kFasLanes;
+    float s = 0.f;
+    if (f < nf) {
+        const int end = fptr[f + 1];
+        for (int j = fptr[f] + lane; j < end; j += kFasLanes) s += z[wperm[j]];
+    }
+#pragma unroll
+    for (int o = kFasLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kFasLanes);
+    double sq = 0.0;
+    if (f < nf && lane == 0) {
+        g[f] = s;
+        sq = (double)s * (double)s;
+    }
+    if (part) block_sum_store(sq, part);
+}
+
+// ----------------------------------------------------------------------------- SBB glue
+
+// g~_f = g_f unless w_f = 0 and g_f > 0 (the bound is active); partial ||g~||^2.
+__global__ __launch_bounds__(kBlock) void k_mask(const float *__restrict__ w, const float *__restrict__ g,
+                                                  float *__restrict__ gt, double *__restrict__ part, int nf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double sq = 0.0;
+    if (i < nf) {
+        const float gi = g[i];
+        const float v = (w[i] > 0.f || gi < 0.f) ? gi : 0.f;
+        gt[i] = v;
+        sq = (double)v * (double)v;
+    }
+    block_sum_store(sq, part);
+}
+
+// alpha from the partial sums (Algorithm 1 (a)/(b)); records the state; i += 1.
+__global__ __launch_bounds__(kBlock) void k_alpha(const double *__restrict__ p_r, int n_r,
+                                                   const double *__restrict__ p_gt, int n_gt,
+                                                   const double *__restrict__ p_vp, int n_vp,
+                                                   const double *__restrict__ p_vpp, int n_vpp,
+                                                   life_sbb_state *__restrict__ st)
+{
+    const int64_t it = st->iter;
+    const bool odd = (it & 1) != 0;
+    const double r2 = block_sum_array(p_r, n_r);
+    const double gt2 = block_sum_array(p_gt, n_gt);
+    const double vp2 = block_sum_array(p_vp, n_vp);
+    const double vpp2 = odd ? 0.0 : block_sum_array(p_vpp, n_vpp);
+    if (threadIdx.x == 0) {
+        const double num = odd ? gt2 : vp2;
+        const double den = odd ? vp2 : vpp2;
+        st->alpha = den > 0.0 ? num / den : 0.0;
+        st->obj = 0.5 * r2;
+        st->gt_norm2 = gt2;
+        st->num = num;
+        st->den = den;
+        st->iter = it + 1;
+    }
+}
+
+// w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.
+__global__ __launch_bounds__(kBlock) void k_update(float *__restrict__ w, const float *__restrict__ gt,
+                                                    const life_sbb_state *__restrict__ st, int nf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nf) return;
+    const double x = (double)w[i] - st->alpha * (double)gt[i];
+    w[i] = x > 0.0 ? (float)x : 0.0f;
+}
+
+int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+// ============================================================================= plan object
+
+struct life_plan_s {
+    life_dims dims{};
+    int device = 0;
+    int slots = 1;                // theta slots per lane, ceil(n_theta / 32) rounded up to a kernel variant
+    // DSC order (voxel, atom, fascicle, input position)
+    int32_t *vox_ptr = nullptr;   // [Nv + 1]
+    int16_t *atom_v = nullptr;    // [nnz]
+    int32_t *fas_v = nullptr;     // [nnz]
+    float *phi_v = nullptr;       // [nnz]
+    // WC order (fascicle, voxel, atom, input position) as DSC positions
+    int32_t *fas_ptr = nullptr;   // [Nf + 1]
+    int32_t *wc_perm = nullptr;   // [nnz]
+    // workspace
+    float *z = nullptr;           // [nnz]
+    float *r = nullptr, *vp = nullptr;             // [Nt*Nv]
+    float *g = nullptr, *gt = nullptr, *vpp = nullptr;  // [Nf]
+    double *part = nullptr;       // 4 regions of part_stride
+    int64_t part_stride = 0;
+    // profiling
+    bool profile = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+hipError_t dalloc(T **p, int64_t n)
+{
+    *p = nullptr;
+    if (n <= 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)n);
+}
+
+void free_plan(life_plan_s *p)
+{
+    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->fas_ptr, p->wc_perm, p->z,
+                    p->r, p->vp, p->g, p->gt, p->vpp, p->part};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    for (auto &e : p->events) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    delete p;
+}
+
+int slots_for(int nth)
+{
+    const int need = (nth + kSeg - 1) / kSeg;
+    static const int variants[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    for (int v : variants)
+        if (v >= need) return v;
+    return 32;
+}
+
+// Launch with optional event bracketing; returns the launch status.
+template <class F>
+life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->profile) {
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
+        if (hipEventRecord(e0, s) != hipSuccess) return LIFE_EDEVICE;
+    }
+    f();
+    const hipError_t err = hipGetLastError();
+    if (p->profile) {
+        if (hipEventRecord(e1, s) != hipSuccess) return LIFE_EDEVICE;
+        p->events.push_back({kind, {e0, e1}});
+    }
+    return err == hipSuccess ? LIFE_OK : LIFE_EDEVICE;
+}
+
+#define LIFE_DISPATCH_SLOTS(SLOTS, KERNEL, ...)                                      \
+    switch (SLOTS) {                                                                 \
+    case 1: KERNEL<1><<<__VA_ARGS__; break;                                          \
+    case 2: KERNEL<2><<<__VA_ARGS__; break;                                          \
+    case 3: KERNEL<3><<<__VA_ARGS__; break;                                          \
+    case 4: KERNEL<4><<<__VA_ARGS__; break;                                          \
+    case 6: KERNEL<6><<<__VA_ARGS__; break;                                          \
+    case 8: KERNEL<8><<<__VA_ARGS__; break;                                          \
+    case 12: KERNEL<12><<<__VA_ARGS__; break;                                        \
+    case 16: KERNEL<16><<<__VA_ARGS__; break;                                        \
+    case 24: KERNEL<24><<<__VA_ARGS__; break;                                        \
+    default: KERNEL<32><<<__VA_ARGS__; break;                                        \
+    }
+
+life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const float *bsub, float *y,
+                        double *part, hipStream_t s)
+{
+    const int nv = p->dims.n_voxels, nth = p->dims.n_theta;
+    if (nv == 0) return LIFE_OK;
+    const int grid = cdiv(nv, kSegPerBlock);
+    return launch(p, LIFE_K_DSC, s, [&] {
+        LIFE_DISPATCH_SLOTS(p->slots, k_dsc, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, w, D,
+                                                                   bsub, y, part, nth, nv))
+    });
+}
+
+life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, double *part,
+                       const life_sbb_state *gate, hipStream_t s)
+{
+    const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
+    life_status st = LIFE_OK;
+    if (nv > 0 && p->dims.nnz > 0) {
+        const int grid = cdiv(nv, kSegPerBlock);
+        st = launch(p, LIFE_K_WC_Z, s, [&] {
+            LIFE_DISPATCH_SLOTS(p->slots, k_wc_z, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->phi_v, D, y, p->z,
+                                                                        nth, nv, gate))
+        });
+        if (st != LIFE_OK) return st;
+    }
+    if (nf > 0) {
+        const int grid = cdiv(nf, kFasPerBlock);
+        st = launch(p, LIFE_K_WC_SUM, s, [&] {
+            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, p->wc_perm, p->z, g, part, nf, gate);
+        });
+    }
+    return st;
+}
+
+}  // namespace
+
+// ============================================================================= C ABI
+
+extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                                 const int32_t *fascicle, const float *phi, life_plan_t *out)
+{
+    if (!out) return LIFE_EINVAL;
+    *out = nullptr;
+    life_status st = life::validate_dims(dims);
+    if (st != LIFE_OK) return st;
+    const life_dims d = *dims;
+    if (d.nnz > 0 && !phi) return LIFE_EINVAL;
+    std::vector<int32_t> perm, vptr, wperm, fptr;
+    std::vector<int16_t> atom_v;
+    std::vector<int32_t> fas_v;
+    std::vector<float> phi_v;
+    try {
+        perm.resize((size_t)d.nnz);
+        wperm.resize((size_t)d.nnz);
+        vptr.resize((size_t)d.n_voxels + 1);
+        fptr.resize((size_t)d.n_fascicles + 1);
+        st = life::plan_host(&d, atom, voxel, fascicle, perm.data(), vptr.data(), wperm.data(), fptr.data());
+        if (st != LIFE_OK) return st;
+        atom_v.resize((size_t)d.nnz);
+        fas_v.resize((size_t)d.nnz);
+        phi_v.resize((size_t)d.nnz);
+        for (int64_t p = 0; p < d.nnz; ++p) {
+            const int32_t c = perm[(size_t)p];
+            atom_v[(size_t)p] = atom[c];
+            fas_v[(size_t)p] = fascicle[c];
+            phi_v[(size_t)p] = phi[c];
+        }
+    } catch (const std::bad_alloc &) {
+        return LIFE_ENOMEM;
+    }
+
+    life_plan_s *p = new (std::nothrow) life_plan_s;
+    if (!p) return LIFE_ENOMEM;
+    p->dims = d;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return LIFE_EDEVICE;
+    }
+    p->slots = slots_for(d.n_theta);
+    const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
+    const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), cdiv(d.n_fascicles, kFasPerBlock),
+                                          cdiv(d.n_fascicles, kBlock), 1});
+    p->part_stride = nb;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dalloc(&p->vox_ptr, d.n_voxels + 1));
+    chk(dalloc(&p->atom_v, d.nnz));
+    chk(dalloc(&p->fas_v, d.nnz));
+    chk(dalloc(&p->phi_v, d.nnz));
+    chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
+    chk(dalloc(&p->wc_perm, d.nnz));
+    chk(dalloc(&p->z, d.nnz));
+    chk(dalloc(&p->r, nsig));
+    chk(dalloc(&p->vp, nsig));
+    chk(dalloc(&p->g, d.n_fascicles));
+    chk(dalloc(&p->gt, d.n_fascicles));
+    chk(dalloc(&p->vpp, d.n_fascicles));
+    chk(dalloc(&p->part, 4 * nb));
+    if (e != hipSuccess) {
+        free_plan(p);
+        return e == hipErrorOutOfMemory ? LIFE_ENOMEM : LIFE_EDEVICE;
+    }
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) chk(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    up(p->vox_ptr, vptr.data(), sizeof(int32_t) * vptr.size());
+    up(p->atom_v, atom_v.data(), sizeof(int16_t) * atom_v.size());
+    up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
+    up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
+    up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());
+    up(p->wc_perm, wperm.data(), sizeof(int32_t) * wperm.size());
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_plan(p);
+        return LIFE_EDEVICE;
+    }
+    *out = p;
+    return LIFE_OK;
+}
+
+extern "C" life_status life_plan_destroy(life_plan_t plan)
+{
+    if (!plan) return LIFE_OK;
+    DeviceGuard g(plan->device);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return g.ok ? LIFE_OK : LIFE_EDEVICE;
+}
+
+extern "C" life_status life_plan_dims(life_plan_t plan, life_dims *out)
+{
+    if (!plan || !out) return LIFE_EINVAL;
+    *out = plan->dims;
+    return LIFE_OK;
+}
+
+extern "C" life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v, int32_t *fas_v,
+                                        float *phi_v, int32_t *fas_ptr, int32_t *wc_perm)
+{
+    if (!plan) return LIFE_EINVAL;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return LIFE_EDEVICE;
+    const life_dims &d = plan->dims;
+    hipError_t e = hipSuccess;
+    auto down = [&](void *dst, const void *src, size_t bytes) {
+        if (dst && bytes && e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    };
+    down(vox_ptr, plan->vox_ptr, sizeof(int32_t) * (size_t)(d.n_voxels + 1));
+    down(atom_v, plan->atom_v, sizeof(int16_t) * (size_t)d.nnz);
+    down(fas_v, plan->fas_v, sizeof(int32_t) * (size_t)d.nnz);
+    down(phi_v, plan->phi_v, sizeof(float) * (size_t)d.nnz);
+    down(fas_ptr, plan->fas_ptr, sizeof(int32_t) * (size_t)(d.n_fascicles + 1));
+    down(wc_perm, plan->wc_perm, sizeof(int32_t) * (size_t)d.nnz);
+    return e == hipSuccess ? LIFE_OK : LIFE_EDEVICE;
+}
+
+static bool need(const void *ptr, int64_t n) { return n == 0 || ptr != nullptr; }
+
+extern "C" life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream)
+{
+    if (!plan) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(w, d.n_fascicles) ||
+        !need(y, (int64_t)d.n_theta * d.n_voxels))
+        return LIFE_EINVAL;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return LIFE_EDEVICE;
+    return enqueue_dsc(plan, D, w, nullptr, y, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream)
+{
+    if (!plan) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(y, (int64_t)d.n_theta * d.n_voxels) ||
+        !need(g, d.n_fascicles))
+        return LIFE_EINVAL;
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    return enqueue_wc(plan, D, y, g, nullptr, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
+                                         life_sbb_state *state, void *stream)
+{
+    if (!plan || !state) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(b, (int64_t)d.n_theta * d.n_voxels) ||
+        !need(w, d.n_fascicles))
+        return LIFE_EINVAL;
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t ps = plan->part_stride;
+    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps, *p_vpp = plan->part + 3 * ps;
+    const int nv = d.n_voxels, nf = d.n_fascicles;
+    const int nb_dsc = nv > 0 ? cdiv(nv, kSegPerBlock) : 0;
+    const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
+    const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
+    life_status st;
+    // r = M w - b, partial ||r||^2
+    if ((st = enqueue_dsc(plan, D, w, b, plan->r, p_r, s)) != LIFE_OK) return st;
+    // g = M^T r
+    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, s)) != LIFE_OK) return st;
+    // g~ and ||g~||^2
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_MASK, s, [&] {
+            k_mask<<<nb_mask, kBlock, 0, s>>>(w, plan->g, plan->gt, p_gt, nf);
+        });
+        if (st != LIFE_OK) return st;
+    }
+    // v' = M g~, ||v'||^2
+    if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
+    // even iterations: v'' = M^T v', ||v''||^2 (the kernels test the parity on the device)
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, p_vpp, state, s)) != LIFE_OK) return st;
+    st = launch(plan, LIFE_K_ALPHA, s, [&] {
+        k_alpha<<<1, kBlock, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, p_vp, nb_dsc, p_vpp, nb_sum, state);
+    });
+    if (st != LIFE_OK) return st;
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_UPDATE, s, [&] {
+            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->gt, state, nf);
+        });
+    }
+    return st;
+}
+
+extern "C" life_status life_profile_enable(life_plan_t plan, int enable)
+{
+    if (!plan) return LIFE_EINVAL;
+    plan->profile = enable != 0;
+    return LIFE_OK;
+}
+
+extern "C" life_status life_profile_read(life_plan_t plan, double *ms, int64_t *count)
+{
+    if (!plan) return LIFE_EINVAL;
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    double acc[LIFE_K_COUNT] = {0};
+    int64_t cnt[LIFE_K_COUNT] = {0};
+    life_status st = LIFE_OK;
+    for (auto &e : plan->events) {
+        float t = 0.f;
+        if (hipEventSynchronize(e.second.second) != hipSuccess ||
+            hipEventElapsedTime(&t, e.second.first, e.second.second) != hipSuccess)
+            st = LIFE_EDEVICE;
+        acc[e.first] += t;
+        cnt[e.first] += 1;
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    plan->events.clear();
+    for (int k = 0; k < LIFE_K_COUNT; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (count) count[k] = cnt[k];
+    }
+    return st;
+}

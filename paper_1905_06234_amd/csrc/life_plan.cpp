@@ -1,0 +1,135 @@
+// Host-side data restructuring for the LiFE sparse-Tucker products.
+//
+// The paper restructures the Phi tensor once, before SBB-NNLS, by sorting its
+// nonzeros on one of the index vectors (Sec. 4.1, "Data Restructuring"): by
+// voxel, so that every voxel's nonzeros form one contiguous "sub-vector"
+// (Sec. 4, sub-vectors of a sorted indirection vector), and - the variant the
+// paper sets aside and this library uses for WC because it needs no atomics -
+// by fiber (fascicle).  Both orders here are total orders, so a plan is unique:
+//   DSC order: (voxel, atom, fascicle, input position)
+//   WC order : (fascicle, voxel, atom, input position)
+// They are built with stable LSD counting sorts, O(nnz + N) per key.
+//
+// Pure C++17: no HIP, so it can be checked on the host alone.
+#include "life_internal.h"
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace life {
+
+life_status validate_dims(const life_dims *d)
+{
+    if (!d) return LIFE_EINVAL;
+    if (d->n_theta < 1 || d->n_theta > kMaxTheta) return LIFE_EINVAL;
+    if (d->n_atoms < 1 || d->n_atoms > 32767) return LIFE_EINVAL;
+    if (d->n_voxels < 0 || d->n_fascicles < 0 || d->nnz < 0) return LIFE_EINVAL;
+    if (d->nnz > kMaxNnz) return LIFE_ERANGE;
+    return LIFE_OK;
+}
+
+life_status validate_indices(const life_dims *d, const int16_t *atom, const int32_t *voxel,
+                             const int32_t *fascicle)
+{
+    const int64_t n = d->nnz;
+    if (n > 0 && (!atom || !voxel || !fascicle)) return LIFE_EINVAL;
+    const int32_t na = d->n_atoms, nv = d->n_voxels, nf = d->n_fascicles;
+    int bad = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        bad |= (atom[c] < 0) | (atom[c] >= na);
+        bad |= (voxel[c] < 0) | (voxel[c] >= nv);
+        bad |= (fascicle[c] < 0) | (fascicle[c] >= nf);
+    }
+    return bad ? LIFE_ERANGE : LIFE_OK;
+}
+
+namespace {
+
+// Stable counting sort of the items in `in` by key(item) in [0, nkeys).
+template <class Key>
+void counting_sort(const int32_t *in, int32_t *out, int64_t n, int64_t nkeys, Key key,
+                   std::vector<int64_t> &cnt)
+{
+    cnt.assign(static_cast<size_t>(nkeys) + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++cnt[static_cast<size_t>(key(in[i])) + 1];
+    for (int64_t k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
+    for (int64_t i = 0; i < n; ++i) out[cnt[static_cast<size_t>(key(in[i]))]++] = in[i];
+}
+
+void segment_offsets(const int32_t *keys_in_order, int64_t n, int32_t nkeys, int32_t *ptr)
+{
+    // keys_in_order is sorted ascending; ptr[k] = first position with key >= k
+    int64_t pos = 0;
+    for (int32_t k = 0; k <= nkeys; ++k) {
+        while (pos < n && keys_in_order[pos] < k) ++pos;
+        ptr[k] = static_cast<int32_t>(pos);
+    }
+}
+
+}  // namespace
+
+life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel,
+                      const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
+                      int32_t *wc_perm, int32_t *fas_ptr)
+{
+    life_status st = validate_dims(d);
+    if (st != LIFE_OK) return st;
+    st = validate_indices(d, atom, voxel, fascicle);
+    if (st != LIFE_OK) return st;
+    const int64_t n = d->nnz;
+    try {
+        std::vector<int32_t> a(static_cast<size_t>(n)), b(static_cast<size_t>(n));
+        std::vector<int64_t> cnt;
+        for (int64_t i = 0; i < n; ++i) a[i] = static_cast<int32_t>(i);
+        // LSD: least significant key first; ties keep input order.
+        counting_sort(a.data(), b.data(), n, d->n_fascicles, [&](int32_t i) { return fascicle[i]; }, cnt);
+        counting_sort(b.data(), a.data(), n, d->n_atoms, [&](int32_t i) { return atom[i]; }, cnt);
+        counting_sort(a.data(), b.data(), n, d->n_voxels, [&](int32_t i) { return voxel[i]; }, cnt);
+        // b = DSC order (voxel, atom, fascicle, input position)
+        if (vox_ptr) {
+            std::vector<int32_t> keys(static_cast<size_t>(n));
+            for (int64_t p = 0; p < n; ++p) keys[p] = voxel[b[p]];
+            segment_offsets(keys.data(), n, d->n_voxels, vox_ptr);
+        }
+        if (wc_perm || fas_ptr) {
+            // Stable sort of DSC positions by fascicle: the DSC order already ranks
+            // (voxel, atom, input position), so ties come out in exactly that order.
+            for (int64_t p = 0; p < n; ++p) a[p] = static_cast<int32_t>(p);
+            std::vector<int32_t> w(static_cast<size_t>(n));
+            counting_sort(a.data(), w.data(), n, d->n_fascicles,
+                          [&](int32_t p) { return fascicle[b[p]]; }, cnt);
+            if (fas_ptr) {
+                std::vector<int32_t> keys(static_cast<size_t>(n));
+                for (int64_t j = 0; j < n; ++j) keys[j] = fascicle[b[w[j]]];
+                segment_offsets(keys.data(), n, d->n_fascicles, fas_ptr);
+            }
+            if (wc_perm && n) std::memcpy(wc_perm, w.data(), sizeof(int32_t) * static_cast<size_t>(n));
+        }
+        if (dsc_perm && n) std::memcpy(dsc_perm, b.data(), sizeof(int32_t) * static_cast<size_t>(n));
+    } catch (const std::bad_alloc &) {
+        return LIFE_ENOMEM;
+    }
+    return LIFE_OK;
+}
+
+}  // namespace life
+
+extern "C" life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                                      const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
+                                      int32_t *wc_perm, int32_t *fas_ptr)
+{
+    return life::plan_host(dims, atom, voxel, fascicle, dsc_perm, vox_ptr, wc_perm, fas_ptr);
+}
+
+extern "C" const char *life_status_str(life_status s)
+{
+    switch (s) {
+    case LIFE_OK: return "LIFE_OK";
+    case LIFE_EINVAL: return "LIFE_EINVAL: invalid argument";
+    case LIFE_ERANGE: return "LIFE_ERANGE: index or size out of range";
+    case LIFE_ENOMEM: return "LIFE_ENOMEM: out of memory";
+    case LIFE_EDEVICE: return "LIFE_EDEVICE: HIP runtime error";
+    }
+    return "LIFE_?: unknown status";
+}

@@ -1,0 +1,232 @@
+"""Python binding of liblife.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module checks shapes, dtypes and
+devices, passes raw device pointers and the current HIP stream, and turns status
+codes into exceptions.  PyTorch serves only as the owner of device memory and
+streams.  If the library is not built, every entry point raises: there is no
+fallback path.
+
+Function names follow the C ABI in include/life.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblife.so")
+
+KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update")
+STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
+STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
+
+
+class LifeError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} {msg}".strip())
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("n_theta", ctypes.c_int32), ("n_atoms", ctypes.c_int32), ("n_voxels", ctypes.c_int32),
+                ("n_fascicles", ctypes.c_int32), ("nnz", ctypes.c_int64)]
+
+
+class SbbState(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int64), ("alpha", ctypes.c_double), ("obj", ctypes.c_double),
+                ("gt_norm2", ctypes.c_double), ("num", ctypes.c_double), ("den", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SIGS = {
+    "life_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P]),
+    "life_plan": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "life_plan_destroy": (ctypes.c_int, [_P]),
+    "life_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(Dims)]),
+    "life_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "life_dsc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "life_wc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "life_sbbnnls_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "life_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "life_profile_read": (ctypes.c_int, [_P, _P, _P]),
+}
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblife.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise LifeError(fn, status)
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _coo(atom, voxel, fascicle):
+    atom = np.ascontiguousarray(atom, dtype=np.int16)
+    voxel = np.ascontiguousarray(voxel, dtype=np.int32)
+    fascicle = np.ascontiguousarray(fascicle, dtype=np.int32)
+    if not (atom.ndim == voxel.ndim == fascicle.ndim == 1 and atom.shape == voxel.shape == fascicle.shape):
+        raise ValueError("atom, voxel, fascicle must be 1-D arrays of one length")
+    return atom, voxel, fascicle
+
+
+def plan_host(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle
+              ) -> Dict[str, np.ndarray]:
+    """Host-only restructuring (life_plan_host): permutations and segment offsets."""
+    atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+    nnz = atom.shape[0]
+    d = Dims(n_theta, n_atoms, n_voxels, n_fascicles, nnz)
+    out = {"dsc_perm": np.empty(nnz, np.int32), "vox_ptr": np.empty(max(n_voxels, 0) + 1, np.int32),
+           "wc_perm": np.empty(nnz, np.int32), "fas_ptr": np.empty(max(n_fascicles, 0) + 1, np.int32)}
+    _check("life_plan_host", load().life_plan_host(ctypes.byref(d), _np_ptr(atom), _np_ptr(voxel),
+                                                   _np_ptr(fascicle), _np_ptr(out["dsc_perm"]),
+                                                   _np_ptr(out["vox_ptr"]), _np_ptr(out["wc_perm"]),
+                                                   _np_ptr(out["fas_ptr"])))
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f32(t, n: int, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements")
+    return ctypes.c_void_p(t.data_ptr()) if n else None
+
+
+def _stream(stream, device):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def new_state(device=None, iteration: int = 0):
+    """A zeroed life_sbb_state on the device (as 6 float64 slots; slot 0 is int64 iter)."""
+    torch = _torch()
+    st = torch.zeros(6, dtype=torch.float64, device=device or "cuda")
+    if iteration:
+        st.view(torch.int64)[0] = iteration
+    return st
+
+
+def read_state(state) -> Dict[str, float]:
+    torch = _torch()
+    host = state.detach().cpu()
+    vals = host.numpy()
+    out = {k: float(vals[i]) for i, k in enumerate(STATE_FIELDS)}
+    out["iter"] = int(host.view(torch.int64)[0])
+    return out
+
+
+class Plan:
+    """A restructured Phi on one device (life_plan); owns its device memory."""
+
+    def __init__(self, n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int,
+                 atom, voxel, fascicle, phi):
+        atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+        phi = np.ascontiguousarray(phi, dtype=np.float32)
+        if phi.shape != atom.shape:
+            raise ValueError("phi must have one value per nonzero")
+        self.dims = Dims(n_theta, n_atoms, n_voxels, n_fascicles, atom.shape[0])
+        self._h = ctypes.c_void_p()
+        lib = load()
+        _check("life_plan", lib.life_plan(ctypes.byref(self.dims), _np_ptr(atom), _np_ptr(voxel),
+                                          _np_ptr(fascicle), _np_ptr(phi), ctypes.byref(self._h)))
+        self.device = _torch().cuda.current_device()
+
+    @classmethod
+    def from_connectome(cls, c) -> "Plan":
+        return cls(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi)
+
+    @property
+    def n_signal(self) -> int:
+        return self.dims.n_theta * self.dims.n_voxels
+
+    def close(self):
+        if self._h:
+            _check("life_plan_destroy", load().life_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _d(self, D):
+        return _dev_f32(D, self.dims.n_theta * self.dims.n_atoms, "D")
+
+    def dsc(self, D, w, y=None, stream=None):
+        """y = M w (life_dsc)."""
+        torch = _torch()
+        if y is None:
+            y = torch.empty(self.n_signal, dtype=torch.float32, device=w.device)
+        _check("life_dsc", load().life_dsc(self._h, self._d(D), _dev_f32(w, self.dims.n_fascicles, "w"),
+                                           _dev_f32(y, self.n_signal, "y"), _stream(stream, w.device)))
+        return y
+
+    def wc(self, D, y, g=None, stream=None):
+        """g = M^T y (life_wc)."""
+        torch = _torch()
+        if g is None:
+            g = torch.empty(self.dims.n_fascicles, dtype=torch.float32, device=y.device)
+        _check("life_wc", load().life_wc(self._h, self._d(D), _dev_f32(y, self.n_signal, "y"),
+                                         _dev_f32(g, self.dims.n_fascicles, "g"), _stream(stream, y.device)))
+        return g
+
+    def sbbnnls_step(self, D, b, w, state, stream=None):
+        """One SBB-NNLS iteration in place on w; state from new_state()."""
+        torch = _torch()
+        if not (isinstance(state, torch.Tensor) and state.is_cuda and state.numel() * state.element_size() == 48
+                and state.is_contiguous()):
+            raise ValueError("state must be a 48-byte contiguous device tensor (see new_state)")
+        _check("life_sbbnnls_step",
+               load().life_sbbnnls_step(self._h, self._d(D), _dev_f32(b, self.n_signal, "b"),
+                                        _dev_f32(w, self.dims.n_fascicles, "w"), ctypes.c_void_p(state.data_ptr()),
+                                        _stream(stream, w.device)))
+        return w
+
+    def export(self) -> Dict[str, np.ndarray]:
+        """The plan's device arrays, copied to host (life_plan_export)."""
+        d = self.dims
+        out = {"vox_ptr": np.empty(d.n_voxels + 1, np.int32), "atom_v": np.empty(d.nnz, np.int16),
+               "fas_v": np.empty(d.nnz, np.int32), "phi_v": np.empty(d.nnz, np.float32),
+               "fas_ptr": np.empty(d.n_fascicles + 1, np.int32), "wc_perm": np.empty(d.nnz, np.int32)}
+        _check("life_plan_export", load().life_plan_export(
+            self._h, *(_np_ptr(out[k]) for k in ("vox_ptr", "atom_v", "fas_v", "phi_v", "fas_ptr", "wc_perm"))))
+        return out
+
+    def profile_enable(self, on: bool = True):
+        _check("life_profile_enable", load().life_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self) -> Tuple[Dict[str, float], Dict[str, int]]:
+        ms = np.zeros(len(KERNELS), np.float64)
+        cnt = np.zeros(len(KERNELS), np.int64)
+        _check("life_profile_read", load().life_profile_read(self._h, _np_ptr(ms), _np_ptr(cnt)))
+        return dict(zip(KERNELS, ms.tolist())), dict(zip(KERNELS, cnt.tolist()))
