@@ -83,7 +83,9 @@ typedef enum {
     LIFE_K_MASK = 3,       /* projected gradient g~ and ||g~||^2 partials          */
     LIFE_K_ALPHA = 4,      /* step length from the partial sums                   */
     LIFE_K_UPDATE = 5,     /* w <- [w - alpha g~]_+                               */
-    LIFE_K_COUNT = 6
+    LIFE_K_WC_Z_EVEN = 6,  /* WC pass 1 of v'' = M^T v' (runs on even i only)     */
+    LIFE_K_WC_SUM_EVEN = 7,/* WC pass 2 of v'' (runs on even i only)              */
+    LIFE_K_COUNT = 8
 } life_kernel_kind;
 
 /* Human-readable name of a status code (static string; never NULL). */
@@ -163,7 +165,9 @@ life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, 
                               life_sbb_state *state, void *stream);
 
 /* Profiling hooks for the benchmark: when enabled, every kernel the plan
- * launches is bracketed by HIP events on its stream.  life_profile_read
+ * launches is bracketed by HIP events on its stream.  The two even-only WC
+ * launches of life_sbbnnls_step are recorded under their own kinds: on odd
+ * iterations they are enqueued but return at once.  life_profile_read
  * synchronizes those events, writes per-kind total milliseconds and launch
  * counts (arrays of LIFE_K_COUNT entries, host; either may be NULL) and
  * resets the record. */

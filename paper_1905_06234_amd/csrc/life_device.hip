@@ -1,17 +1,28 @@
 // HIP (gfx950) kernels and the C ABI of the LiFE sparse-Tucker products.
 //
 // DSC  y = M w   (eq. 1, M_v = D Phi_v of eq. 3): a voxel-segmented reduction
-//      over the voxel-sorted nonzeros.  32 lanes own one voxel; lane l holds
-//      the accumulators y[l + 32k] of that voxel in registers for the whole
-//      segment, so y is written exactly once and no atomics are needed.
+//      over the voxel-sorted nonzeros; every y column is accumulated in
+//      registers and written exactly once (no atomics).
 // WC   g = M^T y  (the transpose product of eq. 6), in two deterministic passes:
-//      (1) voxel-major: the voxel's signal column stays in registers while each
-//          of its nonzeros c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
+//      (1) voxel-major: a voxel's signal column stays in registers while each of
+//          its nonzeros c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
 //      (2) fascicle-major: g[f] = sum of z over the fascicle's nonzeros, read
 //          through the fascicle-sorted permutation, in a fixed tree order.
 // SBB  one SBB-NNLS iteration (Algorithm 1) chains these with a mask kernel, a
 //      one-block step-length kernel and an update kernel; every scalar stays on
 //      the device and every reduction has a fixed order.
+//
+// Two implementations of DSC and WC pass 1 exist:
+//   chunked (n_theta <= 128): a 1024-thread workgroup owns 64 voxels; the
+//     dictionary is staged in LDS one atom tile at a time (3 tiles of 353 atoms
+//     for N_theta = 96, 135.5 KB); inside a wave, eight 8-lane groups each take
+//     one nonzero per step, lane l of a group holding theta = 32c + 4l .. +3, so
+//     a step is 3 ds_read_b128 + 12 FMA per lane.  The per-nonzero scalars are
+//     loaded coalesced once per 64 nonzeros and broadcast inside each group with
+//     ds_swizzle.  This replaces the paper's one-warp-per-sub-vector mapping,
+//     which on a 64-wide wavefront with N_theta = 96 would idle lanes and read D
+//     through the cache hierarchy at 384 B per nonzero.
+//   generic (any n_theta <= 1024): 32 lanes per voxel, D read through L1/L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,20 +34,27 @@
 
 #include "life_internal.h"
 
+using life::kChunkVoxels;
+using life::kChunkWaves;
+using life::kWaveVoxels;
+
 namespace {
 
-constexpr int kBlock = 256;                  // threads per block (4 wave64)
-constexpr int kSeg = 32;                     // lanes per voxel segment
-constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block
+constexpr int kBlock = 256;                  // threads per block of the generic / glue kernels
+constexpr int kSeg = 32;                     // lanes per voxel segment (generic kernels)
+constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block (generic kernels)
 constexpr int kFasLanes = 16;                // lanes per fascicle in the WC sum
 constexpr int kFasPerBlock = kBlock / kFasLanes;
+constexpr int kWG = kChunkWaves * 64;        // threads per chunk workgroup
+constexpr int kAlphaThreads = 1024;
 
 // ----------------------------------------------------------------------------- device helpers
 
 // Sum a double over the block in a fixed order and store it at out[blockIdx.x].
+template <int NT>
 __device__ __forceinline__ void block_sum_store(double v, double *out)
 {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[NT / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -44,20 +62,20 @@ __device__ __forceinline__ void block_sum_store(double v, double *out)
     if (threadIdx.x == 0) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+        for (int i = 0; i < NT / 64; ++i) s += sh[i];
         out[blockIdx.x] = s;
     }
 }
 
-// Fixed-order sum of n doubles by one block; the result is valid in thread 0.
+// Fixed-order sum of n doubles by one block of kAlphaThreads; valid in every thread.
 __device__ double block_sum_array(const double *a, int n)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kAlphaThreads];
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += a[i];
+    for (int i = threadIdx.x; i < n; i += kAlphaThreads) s += a[i];
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = kAlphaThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
@@ -66,7 +84,243 @@ __device__ double block_sum_array(const double *a, int n)
     return r;
 }
 
-// ----------------------------------------------------------------------------- DSC
+// Broadcast lane K of every aligned 8-lane group to the whole group (ds_swizzle,
+// bit-mask mode inside each 32-lane half: and 0x18, or K).
+template <int K>
+__device__ __forceinline__ int bcast8(int x)
+{
+    return __builtin_amdgcn_ds_swizzle(x, 0x18 | (K << 5));
+}
+template <int K>
+__device__ __forceinline__ float bcast8f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x18 | (K << 5)));
+}
+
+// ----------------------------------------------------------------------------- chunked kernels
+
+// Stage atoms [a0, a0 + nrow) of D into LDS rows of ROW floats (zero padded).
+// vec: rows are contiguous (ROW == nth) and D is 16-byte aligned.
+template <int ROW>
+__device__ __forceinline__ void stage_tile(float *lds, const float *__restrict__ D, int a0, int nrow, int nth,
+                                           bool vec)
+{
+    if (vec) {
+        // rows are contiguous in D: plain float4 copy
+        const float4 *src = reinterpret_cast<const float4 *>(D + (size_t)a0 * nth);
+        float4 *dst = reinterpret_cast<float4 *>(lds);
+        const int n4 = nrow * (ROW / 4);
+        for (int i = threadIdx.x; i < n4; i += kWG) dst[i] = src[i];
+    } else {
+        const int n = nrow * ROW;
+        for (int i = threadIdx.x; i < n; i += kWG) {
+            const int r = i / ROW, c = i - r * ROW;
+            lds[i] = c < nth ? D[(size_t)(a0 + r) * nth + c] : 0.f;
+        }
+    }
+}
+
+// DSC: y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
+// NC = 32-float chunks per LDS row (N_theta <= 32 NC).
+template <int NC>
+__global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_vox,
+                                                   const int32_t *__restrict__ tptr,
+                                                   const int16_t *__restrict__ atom,
+                                                   const int32_t *__restrict__ fas,
+                                                   const float *__restrict__ phi,
+                                                   const float *__restrict__ w,
+                                                   const float *__restrict__ D,
+                                                   const float *__restrict__ bsub,
+                                                   float *__restrict__ y, double *__restrict__ part,
+                                                   int nth, int na, int T, int TA, bool vec)
+{
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    constexpr int ROW = NC * 32;
+    constexpr int PER = NC * 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 3, l8 = lane & 7;
+    const int mypos = 8 * l8 + g;          // batch slot whose scalars this lane loads
+    int vox[kWaveVoxels];
+#pragma unroll
+    for (int j = 0; j < kWaveVoxels; ++j) vox[j] = chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j];
+    float acc[kWaveVoxels][PER];
+#pragma unroll
+    for (int j = 0; j < kWaveVoxels; ++j)
+#pragma unroll
+        for (int e = 0; e < PER; ++e) acc[j][e] = 0.f;
+
+    for (int t = 0; t < T; ++t) {
+        const int a0 = t * TA;
+        __syncthreads();
+        stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kWaveVoxels; ++j) {
+            const int v = vox[j];
+            if (v < 0) continue;
+            const int p0 = tptr[(size_t)v * (T + 1) + t], p1 = tptr[(size_t)v * (T + 1) + t + 1];
+            for (int base = p0; base < p1; base += 64) {
+                const int m = min(64, p1 - base);
+                int aoff = 0;                   // row offset only: each lane adds its own column
+                float s = 0.f;
+                if (mypos < m) {
+                    const int c = base + mypos;
+                    aoff += (atom[c] - a0) * ROW;
+                    s = phi[c] * w[fas[c]];     // loop-invariant product hoisted (Sec. 4.1)
+                }
+#define LIFE_DSC_STEP(K)                                                                  \
+    if (8 * K < m) {                                                                      \
+        const int ak = bcast8<K>(aoff) + 4 * l8;                                                   \
+        const float sk = bcast8f<K>(s);                                                   \
+        if (sk != 0.f) {                                                                  \
+            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                           \
+                const float4 d = *reinterpret_cast<const float4 *>(lds + ak + 32 * cc);   \
+                acc[j][4 * cc + 0] = fmaf(d.x, sk, acc[j][4 * cc + 0]);                   \
+                acc[j][4 * cc + 1] = fmaf(d.y, sk, acc[j][4 * cc + 1]);                   \
+                acc[j][4 * cc + 2] = fmaf(d.z, sk, acc[j][4 * cc + 2]);                   \
+                acc[j][4 * cc + 3] = fmaf(d.w, sk, acc[j][4 * cc + 3]);                   \
+            }                                                                             \
+        }                                                                                 \
+    }
+                LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
+                LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
+#undef LIFE_DSC_STEP
+            }
+        }
+    }
+
+    // combine the eight group partials (fixed butterfly) and write each column once
+    double sq = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWaveVoxels; ++j) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            float x = acc[j][e];
+            x += __shfl_xor(x, 8, 64);
+            x += __shfl_xor(x, 16, 64);
+            x += __shfl_xor(x, 32, 64);
+            acc[j][e] = x;
+        }
+        const int v = vox[j];
+        if (v >= 0 && g == 0) {
+            float *yv = y + (size_t)v * nth;
+            const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int th = 32 * cc + 4 * l8 + q;
+                    if (th < nth) {
+                        float r = acc[j][4 * cc + q];
+                        if (bv) r -= bv[th];
+                        yv[th] = r;
+                        sq += (double)r * (double)r;
+                    }
+                }
+        }
+    }
+    if (part) block_sum_store<kWG>(sq, part);
+}
+
+// WC pass 1: z[c] = phi_c * <D[:, atom_c], y[:, v]> for every nonzero c (DSC order).
+template <int NC>
+__global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_vox,
+                                                   const int32_t *__restrict__ tptr,
+                                                   const int16_t *__restrict__ atom,
+                                                   const float *__restrict__ phi,
+                                                   const float *__restrict__ D,
+                                                   const float *__restrict__ y,
+                                                   float *__restrict__ z, int nth, int na, int T, int TA,
+                                                   bool vec, const life_sbb_state *__restrict__ gate)
+{
+    if (gate && (gate->iter & 1)) return;   // even-iteration launch: uniform exit on odd i
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    constexpr int ROW = NC * 32;
+    constexpr int PER = NC * 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 3, l8 = lane & 7;
+    const int mypos = 8 * l8 + g;
+    int vox[kWaveVoxels];
+    float yv[kWaveVoxels][PER];
+#pragma unroll
+    for (int j = 0; j < kWaveVoxels; ++j) {
+        const int v = chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j];
+        vox[j] = v;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int th = 32 * cc + 4 * l8 + q;
+                yv[j][4 * cc + q] = (v >= 0 && th < nth) ? y[(size_t)v * nth + th] : 0.f;
+            }
+    }
+
+    for (int t = 0; t < T; ++t) {
+        const int a0 = t * TA;
+        __syncthreads();
+        stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kWaveVoxels; ++j) {
+            const int v = vox[j];
+            if (v < 0) continue;
+            const int p0 = tptr[(size_t)v * (T + 1) + t], p1 = tptr[(size_t)v * (T + 1) + t + 1];
+            for (int base = p0; base < p1; base += 64) {
+                const int m = min(64, p1 - base);
+                int aoff = 0;                   // row offset only: each lane adds its own column
+                float ph = 0.f;
+                if (mypos < m) {
+                    aoff += (atom[base + mypos] - a0) * ROW;
+                    ph = phi[base + mypos];
+                }
+                float p[8];
+#define LIFE_WCZ_STEP(K)                                                                  \
+    p[K] = 0.f;                                                                           \
+    if (8 * K < m) {                                                                      \
+        const int ak = bcast8<K>(aoff) + 4 * l8;                                                   \
+        float q0 = 0.f;                                                                   \
+        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
+            const float4 d = *reinterpret_cast<const float4 *>(lds + ak + 32 * cc);       \
+            q0 = fmaf(d.x, yv[j][4 * cc + 0], q0);                                        \
+            q0 = fmaf(d.y, yv[j][4 * cc + 1], q0);                                        \
+            q0 = fmaf(d.z, yv[j][4 * cc + 2], q0);                                        \
+            q0 = fmaf(d.w, yv[j][4 * cc + 3], q0);                                        \
+        }                                                                                 \
+        p[K] = q0;                                                                        \
+    }
+                LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
+                LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
+#undef LIFE_WCZ_STEP
+                // transpose-reduce across the 8 lanes of each group: afterwards lane
+                // (g, l8) holds the full dot of step l8, i.e. of batch slot mypos
+                float q4[4], q2[2];
+                const bool b2 = (l8 & 4) != 0, b1 = (l8 & 2) != 0, b0 = (l8 & 1) != 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float send = b2 ? p[i] : p[i + 4];
+                    const float keep = b2 ? p[i + 4] : p[i];
+                    q4[i] = keep + __shfl_xor(send, 4, 64);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const float send = b1 ? q4[i] : q4[i + 2];
+                    const float keep = b1 ? q4[i + 2] : q4[i];
+                    q2[i] = keep + __shfl_xor(send, 2, 64);
+                }
+                {
+                    const float send = b0 ? q2[0] : q2[1];
+                    const float keep = b0 ? q2[1] : q2[0];
+                    const float dot = keep + __shfl_xor(send, 1, 64);
+                    if (mypos < m) z[base + mypos] = ph * dot;
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- generic kernels
 
 // y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
 // NT = accumulator slots per lane: lane l covers theta = l + 32 t, t < NT.
@@ -94,13 +348,13 @@ __global__ __launch_bounds__(kBlock) void k_dsc(const int32_t *__restrict__ vptr
             float s = 0.f;
             if (j < end) {
                 a = atom[j];
-                s = phi[j] * w[fas[j]];     // loop-invariant product hoisted (Sec. 4.1)
+                s = phi[j] * w[fas[j]];
             }
             const int cnt = min(kSeg, end - base);
             for (int k = 0; k < cnt; ++k) {
                 const float sk = __shfl(s, k, kSeg);
                 const int ak = __shfl(a, k, kSeg);
-                if (sk != 0.f) {            // zero weights contribute nothing
+                if (sk != 0.f) {
                     const float *__restrict__ d = D + (size_t)ak * nth + lane;
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
@@ -124,12 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_dsc(const int32_t *__restrict__ vptr
             }
         }
     }
-    if (part) block_sum_store(sq, part);
+    if (part) block_sum_store<kBlock>(sq, part);
 }
 
-// ----------------------------------------------------------------------------- WC
-
-// Pass 1: z[c] = phi_c * <D[:, atom_c], y[:, v]> for every nonzero c, voxel order.
+// WC pass 1 (generic): z[c] = phi_c * <D[:, atom_c], y[:, v]>, 32 lanes per voxel.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vptr,
                                                   const int16_t *__restrict__ atom,
@@ -139,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
                                                   float *__restrict__ z, int nth, int nv,
                                                   const life_sbb_state *__restrict__ gate)
 {
-    if (gate && (gate->iter & 1)) return;   // this launch belongs to even iterations only
+    if (gate && (gate->iter & 1)) return;
     const int lane = threadIdx.x & (kSeg - 1);
     const int v = blockIdx.x * kSegPerBlock + (threadIdx.x / kSeg);
     if (v >= nv) return;
@@ -175,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
     }
 }
 
-// Pass 2: g[f] = sum_{j in seg(f)} z[wperm[j]]  (16 lanes per fascicle, fixed tree).
+// WC pass 2: g[f] = sum_{j in seg(f)} z[wperm[j]]  (16 lanes per fascicle, fixed tree).
 __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
                                                     const int32_t *__restrict__ wperm,
                                                     const float *__restrict__ z,
@@ -197,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
         g[f] = s;
         sq = (double)s * (double)s;
     }
-    if (part) block_sum_store(sq, part);
+    if (part) block_sum_store<kBlock>(sq, part);
 }
 
 // ----------------------------------------------------------------------------- SBB glue
@@ -214,15 +466,15 @@ __global__ __launch_bounds__(kBlock) void k_mask(const float *__restrict__ w, co
         gt[i] = v;
         sq = (double)v * (double)v;
     }
-    block_sum_store(sq, part);
+    block_sum_store<kBlock>(sq, part);
 }
 
 // alpha from the partial sums (Algorithm 1 (a)/(b)); records the state; i += 1.
-__global__ __launch_bounds__(kBlock) void k_alpha(const double *__restrict__ p_r, int n_r,
-                                                   const double *__restrict__ p_gt, int n_gt,
-                                                   const double *__restrict__ p_vp, int n_vp,
-                                                   const double *__restrict__ p_vpp, int n_vpp,
-                                                   life_sbb_state *__restrict__ st)
+__global__ __launch_bounds__(kAlphaThreads) void k_alpha(const double *__restrict__ p_r, int n_r,
+                                                          const double *__restrict__ p_gt, int n_gt,
+                                                          const double *__restrict__ p_vp, int n_vp,
+                                                          const double *__restrict__ p_vpp, int n_vpp,
+                                                          life_sbb_state *__restrict__ st)
 {
     const int64_t it = st->iter;
     const bool odd = (it & 1) != 0;
@@ -261,18 +513,22 @@ int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 struct life_plan_s {
     life_dims dims{};
     int device = 0;
-    int slots = 1;                // theta slots per lane, ceil(n_theta / 32) rounded up to a kernel variant
+    int slots = 1;                // generic kernels: theta slots per lane
+    life::TileGeom tile;          // chunked kernels: LDS tiling (row_floats = 0: not used)
+    int n_chunks = 0;
     // DSC order (voxel, atom, fascicle, input position)
     int32_t *vox_ptr = nullptr;   // [Nv + 1]
     int16_t *atom_v = nullptr;    // [nnz]
     int32_t *fas_v = nullptr;     // [nnz]
     float *phi_v = nullptr;       // [nnz]
+    int32_t *tile_ptr = nullptr;  // [Nv * (n_tiles + 1)]
+    int32_t *chunk_vox = nullptr; // [n_chunks * kChunkVoxels]
     // WC order (fascicle, voxel, atom, input position) as DSC positions
     int32_t *fas_ptr = nullptr;   // [Nf + 1]
     int32_t *wc_perm = nullptr;   // [nnz]
     // workspace
     float *z = nullptr;           // [nnz]
-    float *r = nullptr, *vp = nullptr;             // [Nt*Nv]
+    float *r = nullptr, *vp = nullptr;                  // [Nt*Nv]
     float *g = nullptr, *gt = nullptr, *vpp = nullptr;  // [Nf]
     double *part = nullptr;       // 4 regions of part_stride
     int64_t part_stride = 0;
@@ -308,8 +564,8 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_plan(life_plan_s *p)
 {
-    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->fas_ptr, p->wc_perm, p->z,
-                    p->r, p->vp, p->g, p->gt, p->vpp, p->part};
+    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->tile_ptr, p->chunk_vox, p->fas_ptr, p->wc_perm,
+                    p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->part};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -360,11 +616,58 @@ life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
     default: KERNEL<32><<<__VA_ARGS__; break;                                        \
     }
 
+#define LIFE_DISPATCH_NC(NCV, KERNEL, ...)                                           \
+    switch (NCV) {                                                                   \
+    case 1: KERNEL<1><<<__VA_ARGS__; break;                                          \
+    case 2: KERNEL<2><<<__VA_ARGS__; break;                                          \
+    case 3: KERNEL<3><<<__VA_ARGS__; break;                                          \
+    default: KERNEL<4><<<__VA_ARGS__; break;                                         \
+    }
+
+bool chunked(const life_plan_s *p) { return p->tile.row_floats > 0 && p->n_chunks > 0; }
+
+bool vec_tile(const life_plan_s *p, const float *D)
+{
+    return p->tile.row_floats == p->dims.n_theta && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+}
+
+size_t tile_lds_bytes(const life_plan_s *p) { return (size_t)p->tile.tile_atoms * p->tile.row_floats * sizeof(float); }
+
+// The chunked kernels may use up to the full LDS budget; set once per process so
+// that plans with different tilings never lower each other's limit.
+hipError_t allow_lds()
+{
+    const int bytes = life::kLdsBudget;
+    const void *fns[] = {(const void *)k_dsc_chunk<1>, (const void *)k_dsc_chunk<2>, (const void *)k_dsc_chunk<3>,
+                         (const void *)k_dsc_chunk<4>, (const void *)k_wcz_chunk<1>, (const void *)k_wcz_chunk<2>,
+                         (const void *)k_wcz_chunk<3>, (const void *)k_wcz_chunk<4>};
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int dsc_partials(const life_plan_s *p)
+{
+    return chunked(p) ? p->n_chunks : cdiv(p->dims.n_voxels, kSegPerBlock);
+}
+
 life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const float *bsub, float *y,
                         double *part, hipStream_t s)
 {
     const int nv = p->dims.n_voxels, nth = p->dims.n_theta;
     if (nv == 0) return LIFE_OK;
+    if (chunked(p)) {
+        const int nc = p->tile.row_floats / 32;
+        const size_t lds = tile_lds_bytes(p);
+        return launch(p, LIFE_K_DSC, s, [&] {
+            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->tile_ptr, p->atom_v,
+                                                                           p->fas_v, p->phi_v, w, D, bsub, y, part,
+                                                                           nth, p->dims.n_atoms, p->tile.n_tiles,
+                                                                           p->tile.tile_atoms, vec_tile(p, D)))
+        });
+    }
     const int grid = cdiv(nv, kSegPerBlock);
     return launch(p, LIFE_K_DSC, s, [&] {
         LIFE_DISPATCH_SLOTS(p->slots, k_dsc, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, w, D,
@@ -378,16 +681,29 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
     const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
     life_status st = LIFE_OK;
     if (nv > 0 && p->dims.nnz > 0) {
-        const int grid = cdiv(nv, kSegPerBlock);
-        st = launch(p, LIFE_K_WC_Z, s, [&] {
-            LIFE_DISPATCH_SLOTS(p->slots, k_wc_z, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->phi_v, D, y, p->z,
-                                                                        nth, nv, gate))
-        });
+        const int kind = gate ? LIFE_K_WC_Z_EVEN : LIFE_K_WC_Z;
+        if (chunked(p)) {
+            const int nc = p->tile.row_floats / 32;
+            const size_t lds = tile_lds_bytes(p);
+            st = launch(p, kind, s, [&] {
+                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->tile_ptr, p->atom_v,
+                                                                               p->phi_v, D, y, p->z, nth,
+                                                                               p->dims.n_atoms, p->tile.n_tiles,
+                                                                               p->tile.tile_atoms, vec_tile(p, D),
+                                                                               gate))
+            });
+        } else {
+            const int grid = cdiv(nv, kSegPerBlock);
+            st = launch(p, kind, s, [&] {
+                LIFE_DISPATCH_SLOTS(p->slots, k_wc_z, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->phi_v, D, y,
+                                                                            p->z, nth, nv, gate))
+            });
+        }
         if (st != LIFE_OK) return st;
     }
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
-        st = launch(p, LIFE_K_WC_SUM, s, [&] {
+        st = launch(p, gate ? LIFE_K_WC_SUM_EVEN : LIFE_K_WC_SUM, s, [&] {
             k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, p->wc_perm, p->z, g, part, nf, gate);
         });
     }
@@ -407,10 +723,12 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     if (st != LIFE_OK) return st;
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
-    std::vector<int32_t> perm, vptr, wperm, fptr;
+    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox;
     std::vector<int16_t> atom_v;
     std::vector<int32_t> fas_v;
     std::vector<float> phi_v;
+    const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
+    const int n_chunks = tg.row_floats > 0 ? cdiv(d.n_voxels, kChunkVoxels) : 0;
     try {
         perm.resize((size_t)d.nnz);
         wperm.resize((size_t)d.nnz);
@@ -427,6 +745,11 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
             fas_v[(size_t)p] = fascicle[c];
             phi_v[(size_t)p] = phi[c];
         }
+        if (n_chunks > 0) {
+            tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
+            cvox.resize((size_t)n_chunks * kChunkVoxels);
+            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), tptr.data(), cvox.data());
+        }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;
     }
@@ -439,9 +762,11 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
         return LIFE_EDEVICE;
     }
     p->slots = slots_for(d.n_theta);
+    p->tile = tg;
+    p->n_chunks = n_chunks;
     const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
-    const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), cdiv(d.n_fascicles, kFasPerBlock),
-                                          cdiv(d.n_fascicles, kBlock), 1});
+    const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
+                                          cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
     p->part_stride = nb;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -449,6 +774,8 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     chk(dalloc(&p->atom_v, d.nnz));
     chk(dalloc(&p->fas_v, d.nnz));
     chk(dalloc(&p->phi_v, d.nnz));
+    chk(dalloc(&p->tile_ptr, (int64_t)tptr.size()));
+    chk(dalloc(&p->chunk_vox, (int64_t)cvox.size()));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
     chk(dalloc(&p->wc_perm, d.nnz));
     chk(dalloc(&p->z, d.nnz));
@@ -458,6 +785,7 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     chk(dalloc(&p->gt, d.n_fascicles));
     chk(dalloc(&p->vpp, d.n_fascicles));
     chk(dalloc(&p->part, 4 * nb));
+    if (e == hipSuccess && n_chunks > 0) e = allow_lds();
     if (e != hipSuccess) {
         free_plan(p);
         return e == hipErrorOutOfMemory ? LIFE_ENOMEM : LIFE_EDEVICE;
@@ -469,6 +797,8 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     up(p->atom_v, atom_v.data(), sizeof(int16_t) * atom_v.size());
     up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
     up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
+    up(p->tile_ptr, tptr.data(), sizeof(int32_t) * tptr.size());
+    up(p->chunk_vox, cvox.data(), sizeof(int32_t) * cvox.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());
     up(p->wc_perm, wperm.data(), sizeof(int32_t) * wperm.size());
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -556,7 +886,7 @@ extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const
     const int64_t ps = plan->part_stride;
     double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps, *p_vpp = plan->part + 3 * ps;
     const int nv = d.n_voxels, nf = d.n_fascicles;
-    const int nb_dsc = nv > 0 ? cdiv(nv, kSegPerBlock) : 0;
+    const int nb_dsc = nv > 0 ? dsc_partials(plan) : 0;
     const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
     const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
     life_status st;
@@ -576,7 +906,7 @@ extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const
     // even iterations: v'' = M^T v', ||v''||^2 (the kernels test the parity on the device)
     if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, p_vpp, state, s)) != LIFE_OK) return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
-        k_alpha<<<1, kBlock, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, p_vp, nb_dsc, p_vpp, nb_sum, state);
+        k_alpha<<<1, kAlphaThreads, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, p_vp, nb_dsc, p_vpp, nb_sum, state);
     });
     if (st != LIFE_OK) return st;
     if (nf > 0) {

@@ -13,6 +13,7 @@
 // Pure C++17: no HIP, so it can be checked on the host alone.
 #include "life_internal.h"
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -111,6 +112,57 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
         return LIFE_ENOMEM;
     }
     return LIFE_OK;
+}
+
+TileGeom tile_geometry(int n_theta, int n_atoms)
+{
+    TileGeom g;
+    const int row = ((n_theta + 31) / 32) * 32;
+    if (row > kMaxTileRowFloats) return g;
+    const int max_atoms = kLdsBudget / (row * 4);
+    const int n_tiles = (n_atoms + max_atoms - 1) / max_atoms;
+    g.row_floats = row;
+    g.n_tiles = n_tiles;
+    g.tile_atoms = (n_atoms + n_tiles - 1) / n_tiles;   // balanced tiles
+    return g;
+}
+
+void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
+                int32_t *tile_ptr, int32_t *chunk_vox)
+{
+    const int nv = d->n_voxels, T = tg.n_tiles;
+    for (int v = 0; v < nv; ++v) {
+        int p = vox_ptr[v];
+        const int end = vox_ptr[v + 1];
+        for (int t = 0; t < T; ++t) {
+            const int lo = t * tg.tile_atoms;
+            while (p < end && atom_sorted[p] < lo) ++p;
+            tile_ptr[(int64_t)v * (T + 1) + t] = p;
+        }
+        tile_ptr[(int64_t)v * (T + 1) + T] = end;
+    }
+    const int nchunks = (nv + kChunkVoxels - 1) / kChunkVoxels;
+    std::vector<int> ids;
+    for (int c = 0; c < nchunks; ++c) {
+        const int v0 = c * kChunkVoxels, v1 = std::min(nv, v0 + kChunkVoxels);
+        ids.clear();
+        for (int v = v0; v < v1; ++v) ids.push_back(v);
+        // longest first; ties by voxel id so the plan is unique
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+            return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
+        });
+        int64_t load[kChunkWaves] = {0};
+        int fill[kChunkWaves] = {0};
+        int32_t *slots = chunk_vox + (int64_t)c * kChunkVoxels;
+        for (int i = 0; i < kChunkVoxels; ++i) slots[i] = -1;
+        for (int v : ids) {
+            int best = -1;
+            for (int wv = 0; wv < kChunkWaves; ++wv)
+                if (fill[wv] < kWaveVoxels && (best < 0 || load[wv] < load[best])) best = wv;
+            slots[best * kWaveVoxels + fill[best]++] = v;
+            load[best] += vox_ptr[v + 1] - vox_ptr[v];
+        }
+    }
 }
 
 }  // namespace life

@@ -19,7 +19,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblife.so")
 
-KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update")
+KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_even", "wc_sum_even")
 STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
 STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
 
