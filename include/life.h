@@ -85,7 +85,8 @@ typedef enum {
     LIFE_K_UPDATE = 5,     /* w <- [w - alpha g~]_+                               */
     LIFE_K_WC_Z_EVEN = 6,  /* WC pass 1 of v'' = M^T v' (runs on even i only)     */
     LIFE_K_WC_SUM_EVEN = 7,/* WC pass 2 of v'' (runs on even i only)              */
-    LIFE_K_COUNT = 8
+    LIFE_K_PERMUTE = 8,    /* weights into the plan's fascicle order              */
+    LIFE_K_COUNT = 9
 } life_kernel_kind;
 
 /* Human-readable name of a status code (static string; never NULL). */
@@ -94,18 +95,24 @@ const char *life_status_str(life_status s);
 /* Restructuring on the host only (no device touched): the data-restructuring
  * step of Sec. 4.1 ("Data Restructuring": voxel-based for DSC; fiber-based,
  * i.e. by fascicle, for WC) as two permutations with their segment offsets.
+ * Fascicles are processed in a locality order: by the mean index of the voxels
+ * they cross (ties and empty fascicles by fascicle index, empty ones last), so
+ * that fascicles handled together touch nearby voxels.
  *   atom, voxel, fascicle: host, nnz entries each (input COO order).
  *   dsc_perm  (host, nnz):          input positions in DSC order, the total order
  *                                   (voxel, atom, fascicle, input position).
  *   vox_ptr   (host, n_voxels+1):   voxel v owns DSC positions [vox_ptr[v], vox_ptr[v+1]).
+ *   fas_rank  (host, n_fascicles):  processing rank of each fascicle (a permutation).
  *   wc_perm   (host, nnz):          for WC slot j, its position in the DSC order; WC
- *                                   slots follow (fascicle, voxel, atom, input position).
- *   fas_ptr   (host, n_fascicles+1): fascicle f owns WC slots [fas_ptr[f], fas_ptr[f+1]).
+ *                                   slots follow (fas_rank[fascicle], voxel, atom,
+ *                                   input position).
+ *   fas_ptr   (host, n_fascicles+1): the fascicle of rank r owns WC slots
+ *                                   [fas_ptr[r], fas_ptr[r+1]).
  * Any output may be NULL (not written).  Errors: LIFE_EINVAL (dims or a needed
  * pointer NULL), LIFE_ERANGE (an index out of range), LIFE_ENOMEM. */
 life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
                            const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                           int32_t *wc_perm, int32_t *fas_ptr);
+                           int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
 
 /* Build a plan on the current HIP device from host COO arrays (Sec. 2.2 Phi
  * vectors; restructuring of Sec. 4.1 done once and amortized over the
@@ -125,10 +132,12 @@ life_status life_plan_destroy(life_plan_t plan);
 life_status life_plan_dims(life_plan_t plan, life_dims *out);
 
 /* Copy the plan's device arrays to host buffers (any may be NULL): the DSC
- * order arrays vox_ptr (n_voxels+1), atom_v, fas_v, phi_v (nnz each), and the
- * WC order arrays fas_ptr (n_fascicles+1) and wc_perm (nnz).  Synchronous. */
+ * order arrays vox_ptr (n_voxels+1), atom_v, fas_v (fascicle ranks), phi_v
+ * (nnz each), fas_rank (n_fascicles) and the WC order arrays fas_ptr
+ * (n_fascicles+1) and wc_perm (nnz), as life_plan_host defines them.
+ * Synchronous. */
 life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v, int32_t *fas_v,
-                             float *phi_v, int32_t *fas_ptr, int32_t *wc_perm);
+                             float *phi_v, int32_t *fas_rank, int32_t *fas_ptr, int32_t *wc_perm);
 
 /* DSC, the diffusion signal computation y = M w (eq. 1; Sec. 2.2, the "daxpy"
  * form of the inner loop): y[t + N_theta*v] = sum over nonzeros c of voxel v of

@@ -15,11 +15,11 @@
 // Two implementations of DSC and WC pass 1 exist:
 //   chunked (n_theta <= 128): a 1024-thread workgroup owns 64 voxels; the
 //     dictionary is staged in LDS one atom tile at a time (3 tiles of 353 atoms
-//     for N_theta = 96, 135.5 KB); inside a wave, eight 8-lane groups each take
-//     one nonzero per step, lane l of a group holding theta = 32c + 4l .. +3, so
-//     a step is 3 ds_read_b128 + 12 FMA per lane.  The per-nonzero scalars are
+//     for N_theta = 96, 135.5 KB); inside a wave, four 16-lane groups each take
+//     one nonzero per step, lane l of a group holding theta = 32c + 2l, 2l + 1, so
+//     a step is 3 ds_read_b64 + 6 FMA per lane.  The per-nonzero scalars are
 //     loaded coalesced once per 64 nonzeros and broadcast inside each group with
-//     ds_swizzle.  This replaces the paper's one-warp-per-sub-vector mapping,
+//     a DPP row broadcast (a VALU move, leaving the LDS pipe to the D reads).  This replaces the paper's one-warp-per-sub-vector mapping,
 //     which on a 64-wide wavefront with N_theta = 96 would idle lanes and read D
 //     through the cache hierarchy at 384 B per nonzero.
 //   generic (any n_theta <= 1024): 32 lanes per voxel, D read through L1/L2.
@@ -120,11 +120,57 @@ __device__ __forceinline__ void stage_tile(float *lds, const float *__restrict__
     }
 }
 
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Broadcast lane K of every 16-lane row to the whole row (DPP row_newbcast: a VALU
+// move, no LDS traffic).
+template <int K>
+__device__ __forceinline__ int bcast16(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xf, 0xf, false);
+}
+template <int K>
+__device__ __forceinline__ float bcast16f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + K, 0xf, 0xf, false));
+}
+
+constexpr int kSE = life::kStepEntries;      // entries per step (= lane groups per wave)
+constexpr int kGL = 64 / kSE;                // lanes per group (16)
+constexpr int kBatch = 64;                   // entries per batch: kGL steps
+
+// Work range of this wave in tile t (see life::chunk_layout): first position q0 and
+// cumulative step counts E1..E4 of its four voxel slots.
+struct WaveRange {
+    int q0, e1, e2, e3, e4;
+    __device__ __forceinline__ WaveRange(const int32_t *__restrict__ wave_work, int t, int T, int wave)
+    {
+        const int32_t *ww = wave_work + ((size_t)(blockIdx.x * T + t) * kChunkWaves + wave) * life::kWorkInts;
+        q0 = uni(ww[0]);
+        e1 = uni(ww[1]);
+        e2 = uni(ww[2]);
+        e3 = uni(ww[3]);
+        e4 = uni(ww[4]);
+    }
+    __device__ __forceinline__ int slot(int step) const { return (step >= e1) + (step >= e2) + (step >= e3); }
+    // in-bounds index of entry e of the range (entries past the end are clamped to
+    // the first one and masked by the caller)
+    __device__ __forceinline__ int index(int e) const { return q0 + (e < kSE * e4 ? e : 0); }
+};
+
+// Lane layout of the chunked kernels: a wave is kSE groups of kGL = 16 lanes; at
+// step k of a batch, group g handles entry kSE*k + g, and lane l of a group holds
+// theta = 32c + 2l + {0, 1} for c < NC (each LDS row read as NC float2 per lane).
+// The lane that loads the scalars of entry kSE*k + g is lane kGL*g + k, so a row
+// broadcast of lane k hands every group its entry.
+
 // DSC: y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
-// NC = 32-float chunks per LDS row (N_theta <= 32 NC).
+// NC = 32-float chunks per LDS row (N_theta <= 32 NC).  Inside a tile every wave
+// walks one contiguous range in batches of 64 entries; the scalars of batch i+2 and
+// the w gather of batch i+1 are in flight while batch i runs.
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_vox,
-                                                   const int32_t *__restrict__ tptr,
+                                                   const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
                                                    const int32_t *__restrict__ fas,
                                                    const float *__restrict__ phi,
@@ -137,13 +183,10 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
-    constexpr int PER = NC * 4;
+    constexpr int PER = NC * 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 3, l8 = lane & 7;
-    const int mypos = 8 * l8 + g;          // batch slot whose scalars this lane loads
-    int vox[kWaveVoxels];
-#pragma unroll
-    for (int j = 0; j < kWaveVoxels; ++j) vox[j] = chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j];
+    const int g = lane / kGL, l16 = lane % kGL;
+    const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j)
@@ -154,65 +197,82 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         const int a0 = t * TA;
         __syncthreads();
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
+        const WaveRange R(wave_work, t, T, wave);
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kWaveVoxels; ++j) {
-            const int v = vox[j];
-            if (v < 0) continue;
-            const int p0 = tptr[(size_t)v * (T + 1) + t], p1 = tptr[(size_t)v * (T + 1) + t + 1];
-            for (int base = p0; base < p1; base += 64) {
-                const int m = min(64, p1 - base);
-                int aoff = 0;                   // row offset only: each lane adds its own column
-                float s = 0.f;
-                if (mypos < m) {
-                    const int c = base + mypos;
-                    aoff += (atom[c] - a0) * ROW;
-                    s = phi[c] * w[fas[c]];     // loop-invariant product hoisted (Sec. 4.1)
-                }
+        if (R.e4 == 0) continue;
+        const int lim = kSE * R.e4, nb = (R.e4 + kGL - 1) / kGL;
+        int ix = R.index(mypos);
+        int a_0 = atom[ix], f_0 = fas[ix];
+        float ph_0 = phi[ix];
+        ix = R.index(kBatch + mypos);
+        int a_1 = atom[ix], f_1 = fas[ix];
+        float ph_1 = phi[ix];
+        float w_0 = w[f_0];
+        for (int i = 0; i < nb; ++i) {
+            ix = R.index(kBatch * (i + 2) + mypos);
+            const int a_2 = atom[ix], f_2 = fas[ix];
+            const float ph_2 = phi[ix];
+            const float w_1 = w[f_1];
+            const bool valid = kBatch * i + mypos < lim;
+            const int aoff = valid ? (a_0 - a0) * ROW : 0;
+            const float s = valid ? ph_0 * w_0 : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
+#define LIFE_FMA2(J, CC, DV)                                                              \
+    acc[J][2 * CC + 0] = fmaf(DV.x, sk, acc[J][2 * CC + 0]);                              \
+    acc[J][2 * CC + 1] = fmaf(DV.y, sk, acc[J][2 * CC + 1]);
 #define LIFE_DSC_STEP(K)                                                                  \
-    if (8 * K < m) {                                                                      \
-        const int ak = bcast8<K>(aoff) + 4 * l8;                                                   \
-        const float sk = bcast8f<K>(s);                                                   \
-        if (sk != 0.f) {                                                                  \
-            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                           \
-                const float4 d = *reinterpret_cast<const float4 *>(lds + ak + 32 * cc);   \
-                acc[j][4 * cc + 0] = fmaf(d.x, sk, acc[j][4 * cc + 0]);                   \
-                acc[j][4 * cc + 1] = fmaf(d.y, sk, acc[j][4 * cc + 1]);                   \
-                acc[j][4 * cc + 2] = fmaf(d.z, sk, acc[j][4 * cc + 2]);                   \
-                acc[j][4 * cc + 3] = fmaf(d.w, sk, acc[j][4 * cc + 3]);                   \
+    {                                                                                     \
+        const int step = kGL * i + K;                                                     \
+        const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
+        const float sk = bcast16f<K>(s);                                                  \
+        if (step < R.e4) {                                                                \
+            float2 dv[NC];                                                                \
+            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc)                             \
+                dv[cc] = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);           \
+            switch (R.slot(step)) {                                                       \
+            case 0: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(0, cc, dv[cc]) } break; \
+            case 1: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(1, cc, dv[cc]) } break; \
+            case 2: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(2, cc, dv[cc]) } break; \
+            default: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(3, cc, dv[cc]) } break; \
             }                                                                             \
         }                                                                                 \
     }
-                LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
-                LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
+            LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
+            LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
+            LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11)
+            LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15)
 #undef LIFE_DSC_STEP
-            }
+#undef LIFE_FMA2
+            a_0 = a_1;
+            ph_0 = ph_1;
+            w_0 = w_1;
+            a_1 = a_2;
+            f_1 = f_2;
+            ph_1 = ph_2;
         }
     }
 
-    // combine the eight group partials (fixed butterfly) and write each column once
+    // combine the group partials (fixed butterfly) and write each column once
     double sq = 0.0;
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             float x = acc[j][e];
-            x += __shfl_xor(x, 8, 64);
             x += __shfl_xor(x, 16, 64);
             x += __shfl_xor(x, 32, 64);
             acc[j][e] = x;
         }
-        const int v = vox[j];
+        const int v = uni(chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j]);
         if (v >= 0 && g == 0) {
             float *yv = y + (size_t)v * nth;
             const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int th = 32 * cc + 4 * l8 + q;
+                for (int q = 0; q < 2; ++q) {
+                    const int th = 32 * cc + 2 * l16 + q;
                     if (th < nth) {
-                        float r = acc[j][4 * cc + q];
+                        float r = acc[j][2 * cc + q];
                         if (bv) r -= bv[th];
                         yv[th] = r;
                         sq += (double)r * (double)r;
@@ -223,10 +283,11 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     if (part) block_sum_store<kWG>(sq, part);
 }
 
-// WC pass 1: z[c] = phi_c * <D[:, atom_c], y[:, v]> for every nonzero c (DSC order).
+// WC pass 1: z[q] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the chunked
+// layout (pad entries give 0).  The scalars of batch i+1 load while batch i runs.
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_vox,
-                                                   const int32_t *__restrict__ tptr,
+                                                   const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
                                                    const float *__restrict__ phi,
                                                    const float *__restrict__ D,
@@ -238,22 +299,20 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
-    constexpr int PER = NC * 4;
+    constexpr int PER = NC * 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 3, l8 = lane & 7;
-    const int mypos = 8 * l8 + g;
-    int vox[kWaveVoxels];
+    const int g = lane / kGL, l16 = lane % kGL;
+    const int mypos = kSE * l16 + g;
     float yv[kWaveVoxels][PER];
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
-        const int v = chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j];
-        vox[j] = v;
+        const int v = uni(chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j]);
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int th = 32 * cc + 4 * l8 + q;
-                yv[j][4 * cc + q] = (v >= 0 && th < nth) ? y[(size_t)v * nth + th] : 0.f;
+            for (int q = 0; q < 2; ++q) {
+                const int th = 32 * cc + 2 * l16 + q;
+                yv[j][2 * cc + q] = (v >= 0 && th < nth) ? y[(size_t)v * nth + th] : 0.f;
             }
     }
 
@@ -261,61 +320,62 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
         const int a0 = t * TA;
         __syncthreads();
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
+        const WaveRange R(wave_work, t, T, wave);
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kWaveVoxels; ++j) {
-            const int v = vox[j];
-            if (v < 0) continue;
-            const int p0 = tptr[(size_t)v * (T + 1) + t], p1 = tptr[(size_t)v * (T + 1) + t + 1];
-            for (int base = p0; base < p1; base += 64) {
-                const int m = min(64, p1 - base);
-                int aoff = 0;                   // row offset only: each lane adds its own column
-                float ph = 0.f;
-                if (mypos < m) {
-                    aoff += (atom[base + mypos] - a0) * ROW;
-                    ph = phi[base + mypos];
-                }
-                float p[8];
+        if (R.e4 == 0) continue;
+        const int lim = kSE * R.e4, nb = (R.e4 + kGL - 1) / kGL;
+        int ix = R.index(mypos);
+        int a_0 = atom[ix];
+        float ph_0 = phi[ix];
+        for (int i = 0; i < nb; ++i) {
+            ix = R.index(kBatch * (i + 1) + mypos);
+            const int a_1 = atom[ix];
+            const float ph_1 = phi[ix];
+            const bool valid = kBatch * i + mypos < lim;
+            const int aoff = valid ? (a_0 - a0) * ROW : 0;
+            float p[kGL];
+#define LIFE_DOT2(J, CC, DV)                                                              \
+    q0 = fmaf(DV.x, yv[J][2 * CC + 0], q0);                                               \
+    q0 = fmaf(DV.y, yv[J][2 * CC + 1], q0);
 #define LIFE_WCZ_STEP(K)                                                                  \
-    p[K] = 0.f;                                                                           \
-    if (8 * K < m) {                                                                      \
-        const int ak = bcast8<K>(aoff) + 4 * l8;                                                   \
+    {                                                                                     \
+        const int step = kGL * i + K;                                                     \
+        const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
         float q0 = 0.f;                                                                   \
-        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
-            const float4 d = *reinterpret_cast<const float4 *>(lds + ak + 32 * cc);       \
-            q0 = fmaf(d.x, yv[j][4 * cc + 0], q0);                                        \
-            q0 = fmaf(d.y, yv[j][4 * cc + 1], q0);                                        \
-            q0 = fmaf(d.z, yv[j][4 * cc + 2], q0);                                        \
-            q0 = fmaf(d.w, yv[j][4 * cc + 3], q0);                                        \
+        if (step < R.e4) {                                                                \
+            float2 dv[NC];                                                                \
+            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc)                             \
+                dv[cc] = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);           \
+            switch (R.slot(step)) {                                                       \
+            case 0: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(0, cc, dv[cc]) } break; \
+            case 1: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(1, cc, dv[cc]) } break; \
+            case 2: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(2, cc, dv[cc]) } break; \
+            default: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(3, cc, dv[cc]) } break; \
+            }                                                                             \
         }                                                                                 \
         p[K] = q0;                                                                        \
     }
-                LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
-                LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
+            LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
+            LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
+            LIFE_WCZ_STEP(8) LIFE_WCZ_STEP(9) LIFE_WCZ_STEP(10) LIFE_WCZ_STEP(11)
+            LIFE_WCZ_STEP(12) LIFE_WCZ_STEP(13) LIFE_WCZ_STEP(14) LIFE_WCZ_STEP(15)
 #undef LIFE_WCZ_STEP
-                // transpose-reduce across the 8 lanes of each group: afterwards lane
-                // (g, l8) holds the full dot of step l8, i.e. of batch slot mypos
-                float q4[4], q2[2];
-                const bool b2 = (l8 & 4) != 0, b1 = (l8 & 2) != 0, b0 = (l8 & 1) != 0;
+#undef LIFE_DOT2
+            // transpose-reduce across the 16 lanes of each group (fixed butterfly):
+            // afterwards lane (g, l16) holds the full dot of step l16 = entry mypos
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float send = b2 ? p[i] : p[i + 4];
-                    const float keep = b2 ? p[i + 4] : p[i];
-                    q4[i] = keep + __shfl_xor(send, 4, 64);
-                }
+            for (int half = kGL / 2; half >= 1; half >>= 1) {
+                const bool hi = (l16 & half) != 0;
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const float send = b1 ? q4[i] : q4[i + 2];
-                    const float keep = b1 ? q4[i + 2] : q4[i];
-                    q2[i] = keep + __shfl_xor(send, 2, 64);
-                }
-                {
-                    const float send = b0 ? q2[0] : q2[1];
-                    const float keep = b0 ? q2[1] : q2[0];
-                    const float dot = keep + __shfl_xor(send, 1, 64);
-                    if (mypos < m) z[base + mypos] = ph * dot;
+                for (int k = 0; k < half; ++k) {
+                    const float send = hi ? p[k] : p[k + half];
+                    const float keep = hi ? p[k + half] : p[k];
+                    p[k] = keep + __shfl_xor(send, half, 64);
                 }
             }
+            if (valid) z[R.q0 + kBatch * i + mypos] = ph_0 * p[0];
+            a_0 = a_1;
+            ph_0 = ph_1;
         }
     }
 }
@@ -427,10 +487,12 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
     }
 }
 
-// WC pass 2: g[f] = sum_{j in seg(f)} z[wperm[j]]  (16 lanes per fascicle, fixed tree).
+// WC pass 2: g[out(r)] = sum_{j in seg(r)} z[wperm[j]] for the fascicle of rank r
+// (16 lanes per fascicle, fixed tree); out(r) = gmap[r] (caller order) or r.
 __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
                                                     const int32_t *__restrict__ wperm,
                                                     const float *__restrict__ z,
+                                                    const int32_t *__restrict__ gmap,
                                                     float *__restrict__ g, double *__restrict__ part,
                                                     int nf, const life_sbb_state *__restrict__ gate)
 {
@@ -446,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
     for (int o = kFasLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kFasLanes);
     double sq = 0.0;
     if (f < nf && lane == 0) {
-        g[f] = s;
+        g[gmap ? gmap[f] : f] = s;
         sq = (double)s * (double)s;
     }
     if (part) block_sum_store<kBlock>(sq, part);
@@ -494,14 +556,24 @@ __global__ __launch_bounds__(kAlphaThreads) void k_alpha(const double *__restric
     }
 }
 
-// w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.
-__global__ __launch_bounds__(kBlock) void k_update(float *__restrict__ w, const float *__restrict__ gt,
+// w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.  The
+// iterate and g~ are in fascicle-rank order; w_out is in the caller's order.
+__global__ __launch_bounds__(kBlock) void k_update(float *__restrict__ w_out, const float *__restrict__ w_rank,
+                                                    const float *__restrict__ gt, const int32_t *__restrict__ ext,
                                                     const life_sbb_state *__restrict__ st, int nf)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nf) return;
-    const double x = (double)w[i] - st->alpha * (double)gt[i];
-    w[i] = x > 0.0 ? (float)x : 0.0f;
+    const double x = (double)w_rank[i] - st->alpha * (double)gt[i];
+    w_out[ext[i]] = x > 0.0 ? (float)x : 0.0f;
+}
+
+// w_rank[r] = w[ext[r]]: weights into fascicle-rank order.
+__global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ w, const int32_t *__restrict__ ext,
+                                                    float *__restrict__ w_rank, int nf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nf) w_rank[i] = w[ext[i]];
 }
 
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -521,12 +593,22 @@ struct life_plan_s {
     int16_t *atom_v = nullptr;    // [nnz]
     int32_t *fas_v = nullptr;     // [nnz]
     float *phi_v = nullptr;       // [nnz]
-    int32_t *tile_ptr = nullptr;  // [Nv * (n_tiles + 1)]
+    // chunked layout (see life::chunk_layout): padded copies of the DSC-order arrays
+    int64_t n_pad = 0;
     int32_t *chunk_vox = nullptr; // [n_chunks * kChunkVoxels]
-    // WC order (fascicle, voxel, atom, input position) as DSC positions
+    int32_t *wave_work = nullptr; // [n_chunks * n_tiles * kChunkWaves * kWorkInts]
+    int16_t *atom_c = nullptr;    // [n_pad]
+    int32_t *fas_c = nullptr;     // [n_pad]
+    float *phi_c = nullptr;       // [n_pad]
+    int32_t *wc_perm_c = nullptr; // [nnz] padded position of each WC slot
+    // fascicles are processed in rank order (fas_v holds ranks)
+    int32_t *fas_rank = nullptr;  // [Nf] rank of each fascicle
+    int32_t *fas_ext = nullptr;   // [Nf] fascicle of each rank
+    // WC order (rank, voxel, atom, input position) as DSC positions
     int32_t *fas_ptr = nullptr;   // [Nf + 1]
     int32_t *wc_perm = nullptr;   // [nnz]
     // workspace
+    float *w_rank = nullptr;      // [Nf] weights in rank order
     float *z = nullptr;           // [nnz]
     float *r = nullptr, *vp = nullptr;                  // [Nt*Nv]
     float *g = nullptr, *gt = nullptr, *vpp = nullptr;  // [Nf]
@@ -564,8 +646,9 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_plan(life_plan_s *p)
 {
-    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->tile_ptr, p->chunk_vox, p->fas_ptr, p->wc_perm,
-                    p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->part};
+    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->wave_work, p->atom_c, p->fas_c,
+                    p->phi_c, p->wc_perm_c, p->fas_rank, p->fas_ext,
+                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->part};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -662,8 +745,8 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
         const int nc = p->tile.row_floats / 32;
         const size_t lds = tile_lds_bytes(p);
         return launch(p, LIFE_K_DSC, s, [&] {
-            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->tile_ptr, p->atom_v,
-                                                                           p->fas_v, p->phi_v, w, D, bsub, y, part,
+            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+                                                                           p->fas_c, p->phi_c, w, D, bsub, y, part,
                                                                            nth, p->dims.n_atoms, p->tile.n_tiles,
                                                                            p->tile.tile_atoms, vec_tile(p, D)))
         });
@@ -675,8 +758,8 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
     });
 }
 
-life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, double *part,
-                       const life_sbb_state *gate, hipStream_t s)
+life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, const int32_t *gmap,
+                       double *part, const life_sbb_state *gate, hipStream_t s)
 {
     const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
     life_status st = LIFE_OK;
@@ -686,8 +769,8 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
             const int nc = p->tile.row_floats / 32;
             const size_t lds = tile_lds_bytes(p);
             st = launch(p, kind, s, [&] {
-                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->tile_ptr, p->atom_v,
-                                                                               p->phi_v, D, y, p->z, nth,
+                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+                                                                               p->phi_c, D, y, p->z, nth,
                                                                                p->dims.n_atoms, p->tile.n_tiles,
                                                                                p->tile.tile_atoms, vec_tile(p, D),
                                                                                gate))
@@ -704,10 +787,20 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
         st = launch(p, gate ? LIFE_K_WC_SUM_EVEN : LIFE_K_WC_SUM, s, [&] {
-            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, p->wc_perm, p->z, g, part, nf, gate);
+            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_c : p->wc_perm, p->z, gmap, g,
+                                             part, nf, gate);
         });
     }
     return st;
+}
+
+life_status enqueue_gather(life_plan_s *p, const float *w, hipStream_t s)
+{
+    const int nf = p->dims.n_fascicles;
+    if (nf == 0) return LIFE_OK;
+    return launch(p, LIFE_K_PERMUTE, s, [&] {
+        k_gather<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, p->fas_ext, p->w_rank, nf);
+    });
 }
 
 }  // namespace
@@ -723,7 +816,11 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     if (st != LIFE_OK) return st;
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
-    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox;
+    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, cpos, wperm_c;
+    std::vector<int16_t> atom_c;
+    std::vector<int32_t> fas_c;
+    std::vector<float> phi_c;
+    int64_t n_pad = 0;
     std::vector<int16_t> atom_v;
     std::vector<int32_t> fas_v;
     std::vector<float> phi_v;
@@ -734,21 +831,48 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
         wperm.resize((size_t)d.nnz);
         vptr.resize((size_t)d.n_voxels + 1);
         fptr.resize((size_t)d.n_fascicles + 1);
-        st = life::plan_host(&d, atom, voxel, fascicle, perm.data(), vptr.data(), wperm.data(), fptr.data());
+        rank.resize((size_t)d.n_fascicles);
+        ext.resize((size_t)d.n_fascicles);
+        st = life::plan_host(&d, atom, voxel, fascicle, perm.data(), vptr.data(), rank.data(), wperm.data(),
+                             fptr.data());
         if (st != LIFE_OK) return st;
+        for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
         atom_v.resize((size_t)d.nnz);
         fas_v.resize((size_t)d.nnz);
         phi_v.resize((size_t)d.nnz);
         for (int64_t p = 0; p < d.nnz; ++p) {
             const int32_t c = perm[(size_t)p];
             atom_v[(size_t)p] = atom[c];
-            fas_v[(size_t)p] = fascicle[c];
+            fas_v[(size_t)p] = rank[(size_t)fascicle[c]];
             phi_v[(size_t)p] = phi[c];
         }
         if (n_chunks > 0) {
             tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
             cvox.resize((size_t)n_chunks * kChunkVoxels);
             life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), tptr.data(), cvox.data());
+            wwork.resize((size_t)n_chunks * tg.n_tiles * kChunkWaves * life::kWorkInts);
+            cpos.resize((size_t)d.nnz);
+            n_pad = life::chunk_layout(&d, tg, tptr.data(), cvox.data(), n_chunks, wwork.data(), cpos.data());
+            if (n_pad > life::kMaxNnz) return LIFE_ERANGE;
+            // pad entries: zero value, an atom of their tile, fascicle rank 0
+            atom_c.assign((size_t)n_pad, 0);
+            fas_c.assign((size_t)n_pad, 0);
+            phi_c.assign((size_t)n_pad, 0.f);
+            for (int c = 0; c < n_chunks; ++c)
+                for (int t = 0; t < tg.n_tiles; ++t)
+                    for (int w = 0; w < kChunkWaves; ++w) {
+                        const int32_t *ww = &wwork[((size_t)(c * tg.n_tiles + t) * kChunkWaves + w) * life::kWorkInts];
+                        for (int64_t q = ww[0]; q < ww[0] + life::kStepEntries * (int64_t)ww[4]; ++q)
+                            atom_c[(size_t)q] = (int16_t)(t * tg.tile_atoms);
+                    }
+            for (int64_t p = 0; p < d.nnz; ++p) {
+                const size_t q = (size_t)cpos[(size_t)p];
+                atom_c[q] = atom_v[(size_t)p];
+                fas_c[q] = fas_v[(size_t)p];
+                phi_c[q] = phi_v[(size_t)p];
+            }
+            wperm_c.resize((size_t)d.nnz);
+            for (int64_t j = 0; j < d.nnz; ++j) wperm_c[(size_t)j] = cpos[(size_t)wperm[(size_t)j]];
         }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;
@@ -764,6 +888,7 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     p->slots = slots_for(d.n_theta);
     p->tile = tg;
     p->n_chunks = n_chunks;
+    p->n_pad = n_pad;
     const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
@@ -774,11 +899,18 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     chk(dalloc(&p->atom_v, d.nnz));
     chk(dalloc(&p->fas_v, d.nnz));
     chk(dalloc(&p->phi_v, d.nnz));
-    chk(dalloc(&p->tile_ptr, (int64_t)tptr.size()));
     chk(dalloc(&p->chunk_vox, (int64_t)cvox.size()));
+    chk(dalloc(&p->wave_work, (int64_t)wwork.size()));
+    chk(dalloc(&p->atom_c, n_pad));
+    chk(dalloc(&p->fas_c, n_pad));
+    chk(dalloc(&p->phi_c, n_pad));
+    chk(dalloc(&p->wc_perm_c, (int64_t)wperm_c.size()));
+    chk(dalloc(&p->fas_rank, d.n_fascicles));
+    chk(dalloc(&p->fas_ext, d.n_fascicles));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
     chk(dalloc(&p->wc_perm, d.nnz));
-    chk(dalloc(&p->z, d.nnz));
+    chk(dalloc(&p->w_rank, d.n_fascicles));
+    chk(dalloc(&p->z, std::max<int64_t>(d.nnz, n_pad)));
     chk(dalloc(&p->r, nsig));
     chk(dalloc(&p->vp, nsig));
     chk(dalloc(&p->g, d.n_fascicles));
@@ -797,8 +929,14 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     up(p->atom_v, atom_v.data(), sizeof(int16_t) * atom_v.size());
     up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
     up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
-    up(p->tile_ptr, tptr.data(), sizeof(int32_t) * tptr.size());
     up(p->chunk_vox, cvox.data(), sizeof(int32_t) * cvox.size());
+    up(p->wave_work, wwork.data(), sizeof(int32_t) * wwork.size());
+    up(p->atom_c, atom_c.data(), sizeof(int16_t) * atom_c.size());
+    up(p->fas_c, fas_c.data(), sizeof(int32_t) * fas_c.size());
+    up(p->phi_c, phi_c.data(), sizeof(float) * phi_c.size());
+    up(p->wc_perm_c, wperm_c.data(), sizeof(int32_t) * wperm_c.size());
+    up(p->fas_rank, rank.data(), sizeof(int32_t) * rank.size());
+    up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());
     up(p->wc_perm, wperm.data(), sizeof(int32_t) * wperm.size());
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -827,7 +965,7 @@ extern "C" life_status life_plan_dims(life_plan_t plan, life_dims *out)
 }
 
 extern "C" life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v, int32_t *fas_v,
-                                        float *phi_v, int32_t *fas_ptr, int32_t *wc_perm)
+                                        float *phi_v, int32_t *fas_rank, int32_t *fas_ptr, int32_t *wc_perm)
 {
     if (!plan) return LIFE_EINVAL;
     DeviceGuard g(plan->device);
@@ -841,6 +979,7 @@ extern "C" life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int1
     down(atom_v, plan->atom_v, sizeof(int16_t) * (size_t)d.nnz);
     down(fas_v, plan->fas_v, sizeof(int32_t) * (size_t)d.nnz);
     down(phi_v, plan->phi_v, sizeof(float) * (size_t)d.nnz);
+    down(fas_rank, plan->fas_rank, sizeof(int32_t) * (size_t)d.n_fascicles);
     down(fas_ptr, plan->fas_ptr, sizeof(int32_t) * (size_t)(d.n_fascicles + 1));
     down(wc_perm, plan->wc_perm, sizeof(int32_t) * (size_t)d.nnz);
     return e == hipSuccess ? LIFE_OK : LIFE_EDEVICE;
@@ -857,7 +996,10 @@ extern "C" life_status life_dsc(life_plan_t plan, const float *D, const float *w
         return LIFE_EINVAL;
     DeviceGuard g(plan->device);
     if (!g.ok) return LIFE_EDEVICE;
-    return enqueue_dsc(plan, D, w, nullptr, y, nullptr, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    life_status st = enqueue_gather(plan, w, s);
+    if (st != LIFE_OK) return st;
+    return enqueue_dsc(plan, D, plan->w_rank, nullptr, y, nullptr, s);
 }
 
 extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream)
@@ -869,7 +1011,7 @@ extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y,
         return LIFE_EINVAL;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_wc(plan, D, y, g, nullptr, nullptr, static_cast<hipStream_t>(stream));
+    return enqueue_wc(plan, D, y, g, plan->fas_ext, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
@@ -890,28 +1032,30 @@ extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const
     const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
     const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
     life_status st;
+    // weights into fascicle-rank order (every vector of the step below stays in it)
+    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
     // r = M w - b, partial ||r||^2
-    if ((st = enqueue_dsc(plan, D, w, b, plan->r, p_r, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
     // g = M^T r
-    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, nullptr, s)) != LIFE_OK) return st;
     // g~ and ||g~||^2
     if (nf > 0) {
         st = launch(plan, LIFE_K_MASK, s, [&] {
-            k_mask<<<nb_mask, kBlock, 0, s>>>(w, plan->g, plan->gt, p_gt, nf);
+            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
         });
         if (st != LIFE_OK) return st;
     }
     // v' = M g~, ||v'||^2
     if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
     // even iterations: v'' = M^T v', ||v''||^2 (the kernels test the parity on the device)
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, p_vpp, state, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, state, s)) != LIFE_OK) return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
         k_alpha<<<1, kAlphaThreads, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, p_vp, nb_dsc, p_vpp, nb_sum, state);
     });
     if (st != LIFE_OK) return st;
     if (nf > 0) {
         st = launch(plan, LIFE_K_UPDATE, s, [&] {
-            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->gt, state, nf);
+            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, state, nf);
         });
     }
     return st;

@@ -13,7 +13,7 @@ life_status validate_indices(const life_dims *d, const int16_t *atom, const int3
                              const int32_t *fascicle);
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel,
                       const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                      int32_t *wc_perm, int32_t *fas_ptr);
+                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
 
 }  // namespace life
 
@@ -44,5 +44,19 @@ TileGeom tile_geometry(int n_theta, int n_atoms);
 // (-1 = empty), balanced inside each chunk by longest-processing-time assignment.
 void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
                 int32_t *tile_ptr, int32_t *chunk_vox);
+
+// Chunked layout: for every (chunk c, tile t, wave w) one contiguous range of the
+// padded arrays holds the tile-t sub-ranges of the wave's voxel slots j = 0..3,
+// each padded with zero-valued entries to a multiple of kStepEntries (one step of
+// the wave's lane groups never mixes voxels).
+// wave_work[((c*T + t)*kChunkWaves + w)*kWorkInts + k]:
+//   k = 0: first position of the range; k = 1..4: cumulative step counts E1..E4
+//   (slot j owns steps [E_j, E_{j+1}), E_0 = 0; kStepEntries entries per step).
+constexpr int kStepEntries = 4;
+// chunk_pos[p] = padded position of canonical DSC position p.  Returns the
+// padded length.  pad_tile[q] = tile of padded position q (for pad entries).
+constexpr int kWorkInts = 5;
+int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
+                     int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
 
 }  // namespace life

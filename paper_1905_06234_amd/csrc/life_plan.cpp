@@ -70,9 +70,26 @@ void segment_offsets(const int32_t *keys_in_order, int64_t n, int32_t nkeys, int
 
 }  // namespace
 
+void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fascicle, int32_t *rank)
+{
+    const int32_t nf = d->n_fascicles;
+    std::vector<double> sum(static_cast<size_t>(nf), 0.0);
+    std::vector<int64_t> cnt(static_cast<size_t>(nf), 0);
+    for (int64_t c = 0; c < d->nnz; ++c) {
+        sum[fascicle[c]] += voxel[c];
+        ++cnt[fascicle[c]];
+    }
+    std::vector<double> key(static_cast<size_t>(nf));
+    for (int32_t f = 0; f < nf; ++f) key[f] = cnt[f] ? sum[f] / static_cast<double>(cnt[f]) : 1e300;
+    std::vector<int32_t> order(static_cast<size_t>(nf));
+    for (int32_t f = 0; f < nf; ++f) order[f] = f;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    for (int32_t r = 0; r < nf; ++r) rank[order[r]] = r;
+}
+
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel,
                       const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                      int32_t *wc_perm, int32_t *fas_ptr)
+                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
 {
     life_status st = validate_dims(d);
     if (st != LIFE_OK) return st;
@@ -93,16 +110,20 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
             for (int64_t p = 0; p < n; ++p) keys[p] = voxel[b[p]];
             segment_offsets(keys.data(), n, d->n_voxels, vox_ptr);
         }
+        std::vector<int32_t> rank(static_cast<size_t>(d->n_fascicles));
+        fascicle_ranks(d, voxel, fascicle, rank.data());
+        if (fas_rank && d->n_fascicles)
+            std::memcpy(fas_rank, rank.data(), sizeof(int32_t) * static_cast<size_t>(d->n_fascicles));
         if (wc_perm || fas_ptr) {
-            // Stable sort of DSC positions by fascicle: the DSC order already ranks
+            // Stable sort of DSC positions by fascicle rank: the DSC order already ranks
             // (voxel, atom, input position), so ties come out in exactly that order.
             for (int64_t p = 0; p < n; ++p) a[p] = static_cast<int32_t>(p);
             std::vector<int32_t> w(static_cast<size_t>(n));
             counting_sort(a.data(), w.data(), n, d->n_fascicles,
-                          [&](int32_t p) { return fascicle[b[p]]; }, cnt);
+                          [&](int32_t p) { return rank[fascicle[b[p]]]; }, cnt);
             if (fas_ptr) {
                 std::vector<int32_t> keys(static_cast<size_t>(n));
-                for (int64_t j = 0; j < n; ++j) keys[j] = fascicle[b[w[j]]];
+                for (int64_t j = 0; j < n; ++j) keys[j] = rank[fascicle[b[w[j]]]];
                 segment_offsets(keys.data(), n, d->n_fascicles, fas_ptr);
             }
             if (wc_perm && n) std::memcpy(wc_perm, w.data(), sizeof(int32_t) * static_cast<size_t>(n));
@@ -165,13 +186,39 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
     }
 }
 
+int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
+                     int n_chunks, int32_t *wave_work, int32_t *chunk_pos)
+{
+    const int T = tg.n_tiles;
+    int64_t q = 0;
+    for (int c = 0; c < n_chunks; ++c)
+        for (int t = 0; t < T; ++t)
+            for (int w = 0; w < kChunkWaves; ++w) {
+                int32_t *ww = wave_work + ((int64_t)(c * T + t) * kChunkWaves + w) * kWorkInts;
+                ww[0] = static_cast<int32_t>(q);
+                int steps = 0;
+                for (int j = 0; j < kWaveVoxels; ++j) {
+                    const int v = chunk_vox[(int64_t)c * kChunkVoxels + w * kWaveVoxels + j];
+                    if (v >= 0) {
+                        const int32_t p0 = tile_ptr[(int64_t)v * (T + 1) + t], p1 = tile_ptr[(int64_t)v * (T + 1) + t + 1];
+                        for (int32_t p = p0; p < p1; ++p) chunk_pos[p] = static_cast<int32_t>(q + (p - p0));
+                        const int ns = (p1 - p0 + kStepEntries - 1) / kStepEntries;
+                        q += kStepEntries * (int64_t)ns;
+                        steps += ns;
+                    }
+                    ww[1 + j] = steps;
+                }
+            }
+    return q;
+}
+
 }  // namespace life
 
 extern "C" life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
                                       const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                                      int32_t *wc_perm, int32_t *fas_ptr)
+                                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
 {
-    return life::plan_host(dims, atom, voxel, fascicle, dsc_perm, vox_ptr, wc_perm, fas_ptr);
+    return life::plan_host(dims, atom, voxel, fascicle, dsc_perm, vox_ptr, fas_rank, wc_perm, fas_ptr);
 }
 
 extern "C" const char *life_status_str(life_status s)

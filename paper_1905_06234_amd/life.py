@@ -19,7 +19,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblife.so")
 
-KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_even", "wc_sum_even")
+KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_even", "wc_sum_even", "permute")
 STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
 STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
 
@@ -44,11 +44,11 @@ _lib = None
 _P = ctypes.c_void_p
 _SIGS = {
     "life_status_str": (ctypes.c_char_p, [ctypes.c_int]),
-    "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P]),
+    "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, _P]),
     "life_plan": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "life_plan_destroy": (ctypes.c_int, [_P]),
     "life_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(Dims)]),
-    "life_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "life_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "life_dsc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_wc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_sbbnnls_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -97,11 +97,12 @@ def plan_host(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom,
     nnz = atom.shape[0]
     d = Dims(n_theta, n_atoms, n_voxels, n_fascicles, nnz)
     out = {"dsc_perm": np.empty(nnz, np.int32), "vox_ptr": np.empty(max(n_voxels, 0) + 1, np.int32),
-           "wc_perm": np.empty(nnz, np.int32), "fas_ptr": np.empty(max(n_fascicles, 0) + 1, np.int32)}
+           "fas_rank": np.empty(max(n_fascicles, 0), np.int32), "wc_perm": np.empty(nnz, np.int32),
+           "fas_ptr": np.empty(max(n_fascicles, 0) + 1, np.int32)}
     _check("life_plan_host", load().life_plan_host(ctypes.byref(d), _np_ptr(atom), _np_ptr(voxel),
                                                    _np_ptr(fascicle), _np_ptr(out["dsc_perm"]),
-                                                   _np_ptr(out["vox_ptr"]), _np_ptr(out["wc_perm"]),
-                                                   _np_ptr(out["fas_ptr"])))
+                                                   _np_ptr(out["vox_ptr"]), _np_ptr(out["fas_rank"]),
+                                                   _np_ptr(out["wc_perm"]), _np_ptr(out["fas_ptr"])))
     return out
 
 
@@ -217,9 +218,10 @@ class Plan:
         d = self.dims
         out = {"vox_ptr": np.empty(d.n_voxels + 1, np.int32), "atom_v": np.empty(d.nnz, np.int16),
                "fas_v": np.empty(d.nnz, np.int32), "phi_v": np.empty(d.nnz, np.float32),
+               "fas_rank": np.empty(d.n_fascicles, np.int32),
                "fas_ptr": np.empty(d.n_fascicles + 1, np.int32), "wc_perm": np.empty(d.nnz, np.int32)}
-        _check("life_plan_export", load().life_plan_export(
-            self._h, *(_np_ptr(out[k]) for k in ("vox_ptr", "atom_v", "fas_v", "phi_v", "fas_ptr", "wc_perm"))))
+        keys = ("vox_ptr", "atom_v", "fas_v", "phi_v", "fas_rank", "fas_ptr", "wc_perm")
+        _check("life_plan_export", load().life_plan_export(self._h, *(_np_ptr(out[k]) for k in keys)))
         return out
 
     def profile_enable(self, on: bool = True):

@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Dict, Optional, Tuple
 
 import numpy as np
@@ -268,8 +269,33 @@ def make(name: str, n_fascicles: Optional[int] = None) -> Connectome:
     """Build configuration ``name`` deterministically from its seed.
 
     ``n_fascicles`` optionally overrides the fascicle count (same seeds; used for
-    reduced variants of a configuration in tests).
+    reduced variants of a configuration in tests).  If the environment variable
+    LIFE_SYNTH_CACHE names a directory, the arrays are cached there as .npz
+    (written by this function only, read back with allow_pickle=False).
     """
+    cache = os.environ.get("LIFE_SYNTH_CACHE")
+    if cache:
+        path = os.path.join(cache, f"{name}_{n_fascicles or 'default'}_v1.npz")
+        if os.path.exists(path):
+            with np.load(path, allow_pickle=False) as z:
+                meta = z["meta"]
+                return Connectome(name=name, n_theta=int(meta[0]), n_atoms=int(meta[1]), n_voxels=int(meta[2]),
+                                  n_fascicles=int(meta[3]), grid=(int(meta[4]), int(meta[5]), int(meta[6])),
+                                  **{k: z[k] for k in _ARRAYS})
+        c = _make(name, n_fascicles)
+        os.makedirs(cache, exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}.npz"
+        np.savez(tmp, meta=np.array([c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, *c.grid]),
+                 **{k: getattr(c, k) for k in _ARRAYS})
+        os.replace(tmp, path)
+        return c
+    return _make(name, n_fascicles)
+
+
+_ARRAYS = ("atom", "voxel", "fascicle", "phi", "D", "w0", "w_true", "noise", "voxel_xyz")
+
+
+def _make(name: str, n_fascicles: Optional[int]) -> Connectome:
     cfg = CONFIGS[name]
     if n_fascicles is not None:
         cfg = dataclasses.replace(cfg, n_fascicles=int(n_fascicles))

@@ -38,3 +38,29 @@ def relerr(x, ref):
     d = np.linalg.norm(x - ref)
     n = np.linalg.norm(ref)
     return float(d / n) if n > 0 else float(d)
+
+
+def reference_plan(c):
+    """The restructuring plan computed independently with numpy.lexsort.
+
+    DSC order (voxel, atom, fascicle, input position); fascicle ranks by mean voxel
+    index (empty fascicles last, ties by index); WC order (rank, voxel, atom,
+    input position) given as DSC positions; segment offsets of both."""
+    pos = np.arange(c.nnz)
+    dsc = np.lexsort((pos, c.fascicle, c.atom, c.voxel))
+    cnt = np.bincount(c.fascicle, minlength=c.n_fascicles)
+    tot = np.bincount(c.fascicle, weights=c.voxel.astype(np.float64), minlength=c.n_fascicles)
+    key = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.inf)
+    order = np.argsort(key, kind="stable")
+    rank = np.empty(c.n_fascicles, np.int64)
+    rank[order] = np.arange(c.n_fascicles)
+    wc_in = np.lexsort((pos, c.atom, c.voxel, rank[c.fascicle]))
+    inv = np.empty(c.nnz, np.int64)
+    inv[dsc] = pos
+    return {
+        "dsc_perm": dsc,
+        "vox_ptr": np.searchsorted(c.voxel[dsc], np.arange(c.n_voxels + 1), side="left"),
+        "fas_rank": rank,
+        "wc_perm": inv[wc_in],
+        "fas_ptr": np.searchsorted(rank[c.fascicle[wc_in]], np.arange(c.n_fascicles + 1), side="left"),
+    }

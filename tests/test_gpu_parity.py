@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import connectome, relerr
+from conftest import connectome, reference_plan, relerr
 
 torch = pytest.importorskip("torch")
 from paper_1905_06234_amd import life  # noqa: E402
@@ -123,17 +123,15 @@ def test_outputs_overwritten(dev):
 def test_device_plan_bit_exact(name, dev):
     c, op, plan = problem(name, dev)
     ex = plan.export()
-    pos = np.arange(c.nnz)
-    dsc = np.lexsort((pos, c.fascicle, c.atom, c.voxel))
-    wc_in = np.lexsort((pos, c.atom, c.voxel, c.fascicle))
-    inv = np.empty(c.nnz, np.int64)
-    inv[dsc] = pos
-    assert np.array_equal(ex["vox_ptr"], np.searchsorted(c.voxel[dsc], np.arange(c.n_voxels + 1)))
+    ref = reference_plan(c)
+    dsc = ref["dsc_perm"]
+    assert np.array_equal(ex["vox_ptr"], ref["vox_ptr"])
     assert np.array_equal(ex["atom_v"], c.atom[dsc])
-    assert np.array_equal(ex["fas_v"], c.fascicle[dsc])
+    assert np.array_equal(ex["fas_v"], ref["fas_rank"][c.fascicle[dsc]])
     assert np.array_equal(ex["phi_v"].view(np.uint32), c.phi[dsc].view(np.uint32))
-    assert np.array_equal(ex["fas_ptr"], np.searchsorted(c.fascicle[wc_in], np.arange(c.n_fascicles + 1)))
-    assert np.array_equal(ex["wc_perm"], inv[wc_in])
+    assert np.array_equal(ex["fas_rank"], ref["fas_rank"])
+    assert np.array_equal(ex["fas_ptr"], ref["fas_ptr"])
+    assert np.array_equal(ex["wc_perm"], ref["wc_perm"])
 
 
 # ----------------------------------------------------------------------------- SBB-NNLS

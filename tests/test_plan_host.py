@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import ROOT, connectome
+from conftest import ROOT, connectome, reference_plan
 from paper_1905_06234_amd import life
 
 HEADER = os.path.join(ROOT, "include", "life.h")
@@ -36,17 +36,6 @@ def test_status_strings():
         assert lib.life_status_str(s).decode().startswith(life.STATUS[s])
 
 
-def _lexsort_plans(c):
-    pos = np.arange(c.nnz)
-    dsc = np.lexsort((pos, c.fascicle, c.atom, c.voxel))           # (voxel, atom, fascicle, pos)
-    wc_in = np.lexsort((pos, c.atom, c.voxel, c.fascicle))          # (fascicle, voxel, atom, pos)
-    inv = np.empty(c.nnz, np.int64)
-    inv[dsc] = np.arange(c.nnz)
-    vox_ptr = np.searchsorted(c.voxel[dsc], np.arange(c.n_voxels + 1), side="left")
-    fas_ptr = np.searchsorted(c.fascicle[wc_in], np.arange(c.n_fascicles + 1), side="left")
-    return dsc, vox_ptr, inv[wc_in], fas_ptr
-
-
 @pytest.mark.parametrize("which", ["tiny", "mid20k", "random_dup", "ragged"])
 def test_host_plan_bit_exact(which):
     if which == "tiny":
@@ -58,11 +47,9 @@ def test_host_plan_bit_exact(which):
     else:
         c = synth.random_coo(3, 5, 9000, 3, 1234, seed=5)   # many empty voxels
     p = life.plan_host(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle)
-    dsc, vox_ptr, wc_perm, fas_ptr = _lexsort_plans(c)
-    assert np.array_equal(p["dsc_perm"], dsc)
-    assert np.array_equal(p["vox_ptr"], vox_ptr)
-    assert np.array_equal(p["wc_perm"], wc_perm)
-    assert np.array_equal(p["fas_ptr"], fas_ptr)
+    ref = reference_plan(c)
+    for k in ("dsc_perm", "vox_ptr", "fas_rank", "wc_perm", "fas_ptr"):
+        assert np.array_equal(p[k], ref[k]), k
 
 
 def test_host_plan_empty():
@@ -98,8 +85,8 @@ def test_bad_dims_rejected(dims):
 def test_null_arguments_rejected():
     lib = life.load()
     d = life.Dims(4, 4, 4, 4, 3)
-    assert lib.life_plan_host(ctypes.byref(d), None, None, None, None, None, None, None) == 1
-    assert lib.life_plan_host(None, None, None, None, None, None, None, None) == 1
+    assert lib.life_plan_host(ctypes.byref(d), None, None, None, None, None, None, None, None) == 1
+    assert lib.life_plan_host(None, None, None, None, None, None, None, None, None) == 1
     h = ctypes.c_void_p()
     assert lib.life_plan(ctypes.byref(d), None, None, None, None, ctypes.byref(h)) == 1
     assert lib.life_dsc(None, None, None, None, None) == 1
