@@ -122,52 +122,62 @@ __device__ __forceinline__ void stage_tile(float *lds, const float *__restrict__
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Broadcast lane K of every 16-lane row to the whole row (DPP row_newbcast: a VALU
-// move, no LDS traffic).
+// DPP moves inside 16-lane rows (VALU only, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+// broadcast lane K of every row to the row (row_newbcast)
 template <int K>
 __device__ __forceinline__ int bcast16(int x)
 {
     return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xf, 0xf, false);
 }
 template <int K>
-__device__ __forceinline__ float bcast16f(float x)
+__device__ __forceinline__ float bcast16f(float x) { return dppf<0x150 + K>(x); }
+// value of lane (l ^ M) inside the row, M in {1, 2, 4, 8}
+template <int M>
+__device__ __forceinline__ float xor16(float x, int l16)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + K, 0xf, 0xf, false));
+    if constexpr (M == 1) return dppf<0xB1>(x);                 // quad_perm [1,0,3,2]
+    else if constexpr (M == 2) return dppf<0x4E>(x);            // quad_perm [2,3,0,1]
+    else if constexpr (M == 8) return dppf<0x128>(x);           // row_ror:8
+    else {
+        const float up = dppf<0x104>(x);                        // row_shl:4 -> lane l gets l + 4
+        const float dn = dppf<0x114>(x);                        // row_shr:4 -> lane l gets l - 4
+        return (l16 & 4) ? dn : up;
+    }
 }
 
 constexpr int kSE = life::kStepEntries;      // entries per step (= lane groups per wave)
 constexpr int kGL = 64 / kSE;                // lanes per group (16)
 constexpr int kBatch = 64;                   // entries per batch: kGL steps
 
-// Work range of this wave in tile t (see life::chunk_layout): first position q0 and
-// cumulative step counts E1..E4 of its four voxel slots.
+// Work range of this wave in tile t (see life::chunk_layout): slot j owns entries
+// [q0 + kSE*E_j, q0 + kSE*E_{j+1}).
 struct WaveRange {
-    int q0, e1, e2, e3, e4;
+    int p[kWaveVoxels + 1];
     __device__ __forceinline__ WaveRange(const int32_t *__restrict__ wave_work, int t, int T, int wave)
     {
         const int32_t *ww = wave_work + ((size_t)(blockIdx.x * T + t) * kChunkWaves + wave) * life::kWorkInts;
-        q0 = uni(ww[0]);
-        e1 = uni(ww[1]);
-        e2 = uni(ww[2]);
-        e3 = uni(ww[3]);
-        e4 = uni(ww[4]);
+        const int q0 = uni(ww[0]);
+        p[0] = q0;
+#pragma unroll
+        for (int j = 1; j <= kWaveVoxels; ++j) p[j] = q0 + kSE * uni(ww[j]);
     }
-    __device__ __forceinline__ int slot(int step) const { return (step >= e1) + (step >= e2) + (step >= e3); }
-    // in-bounds index of entry e of the range (entries past the end are clamped to
-    // the first one and masked by the caller)
-    __device__ __forceinline__ int index(int e) const { return q0 + (e < kSE * e4 ? e : 0); }
 };
 
 // Lane layout of the chunked kernels: a wave is kSE groups of kGL = 16 lanes; at
 // step k of a batch, group g handles entry kSE*k + g, and lane l of a group holds
 // theta = 32c + 2l + {0, 1} for c < NC (each LDS row read as NC float2 per lane).
 // The lane that loads the scalars of entry kSE*k + g is lane kGL*g + k, so a row
-// broadcast of lane k hands every group its entry.
+// broadcast of lane k hands every group its entry.  Batches never span two voxel
+// slots; full batches run 16 branch-free steps, the last batch of a slot is
+// guarded per step.
 
 // DSC: y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
-// NC = 32-float chunks per LDS row (N_theta <= 32 NC).  Inside a tile every wave
-// walks one contiguous range in batches of 64 entries; the scalars of batch i+2 and
-// the w gather of batch i+1 are in flight while batch i runs.
+// NC = 32-float chunks per LDS row (N_theta <= 32 NC).
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
@@ -199,55 +209,52 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
         const WaveRange R(wave_work, t, T, wave);
         __syncthreads();
-        if (R.e4 == 0) continue;
-        const int lim = kSE * R.e4, nb = (R.e4 + kGL - 1) / kGL;
-        int ix = R.index(mypos);
-        int a_0 = atom[ix], f_0 = fas[ix];
-        float ph_0 = phi[ix];
-        ix = R.index(kBatch + mypos);
-        int a_1 = atom[ix], f_1 = fas[ix];
-        float ph_1 = phi[ix];
-        float w_0 = w[f_0];
-        for (int i = 0; i < nb; ++i) {
-            ix = R.index(kBatch * (i + 2) + mypos);
-            const int a_2 = atom[ix], f_2 = fas[ix];
-            const float ph_2 = phi[ix];
-            const float w_1 = w[f_1];
-            const bool valid = kBatch * i + mypos < lim;
-            const int aoff = valid ? (a_0 - a0) * ROW : 0;
-            const float s = valid ? ph_0 * w_0 : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
-#define LIFE_FMA2(J, CC, DV)                                                              \
-    acc[J][2 * CC + 0] = fmaf(DV.x, sk, acc[J][2 * CC + 0]);                              \
-    acc[J][2 * CC + 1] = fmaf(DV.y, sk, acc[J][2 * CC + 1]);
+        if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
+        // scalars of the first batch of the wave's range
+        int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
+        int a_n = atom[ix], f_n = fas[ix];
+        float ph_n = phi[ix];
+#pragma unroll
+        for (int j = 0; j < kWaveVoxels; ++j) {
+            for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
+                const int m = min(kBatch, R.p[j + 1] - b);
+                const int a_c = a_n;
+                const float ph_c = ph_n, w_c = w[f_n];
+                // prefetch the next batch: same slot, else the first batch of a later slot
+                int nxt = b + kBatch < R.p[j + 1] ? b + kBatch : R.p[j + 1];
+                nxt = nxt + mypos < R.p[kWaveVoxels] ? nxt + mypos : R.p[0];
+                a_n = atom[nxt];
+                f_n = fas[nxt];
+                ph_n = phi[nxt];
+                const bool valid = mypos < m;
+                const int aoff = valid ? (a_c - a0) * ROW : 0;
+                const float s = valid ? ph_c * w_c : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
 #define LIFE_DSC_STEP(K)                                                                  \
     {                                                                                     \
-        const int step = kGL * i + K;                                                     \
         const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
         const float sk = bcast16f<K>(s);                                                  \
-        if (step < R.e4) {                                                                \
-            float2 dv[NC];                                                                \
-            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc)                             \
-                dv[cc] = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);           \
-            switch (R.slot(step)) {                                                       \
-            case 0: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(0, cc, dv[cc]) } break; \
-            case 1: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(1, cc, dv[cc]) } break; \
-            case 2: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(2, cc, dv[cc]) } break; \
-            default: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_FMA2(3, cc, dv[cc]) } break; \
-            }                                                                             \
+        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
+            const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
+            acc[j][2 * cc + 0] = fmaf(d.x, sk, acc[j][2 * cc + 0]);                       \
+            acc[j][2 * cc + 1] = fmaf(d.y, sk, acc[j][2 * cc + 1]);                       \
         }                                                                                 \
     }
-            LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
-            LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
-            LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11)
-            LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15)
+                if (m == kBatch) {
+                    LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
+                    LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
+                    LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11)
+                    LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15)
+                } else {
+                    const int ns = m / kSE;     // sub-ranges are padded to whole steps
+#define LIFE_DSC_GSTEP(K) if (K < ns) LIFE_DSC_STEP(K)
+                    LIFE_DSC_GSTEP(0) LIFE_DSC_GSTEP(1) LIFE_DSC_GSTEP(2) LIFE_DSC_GSTEP(3)
+                    LIFE_DSC_GSTEP(4) LIFE_DSC_GSTEP(5) LIFE_DSC_GSTEP(6) LIFE_DSC_GSTEP(7)
+                    LIFE_DSC_GSTEP(8) LIFE_DSC_GSTEP(9) LIFE_DSC_GSTEP(10) LIFE_DSC_GSTEP(11)
+                    LIFE_DSC_GSTEP(12) LIFE_DSC_GSTEP(13) LIFE_DSC_GSTEP(14)
+#undef LIFE_DSC_GSTEP
+                }
 #undef LIFE_DSC_STEP
-#undef LIFE_FMA2
-            a_0 = a_1;
-            ph_0 = ph_1;
-            w_0 = w_1;
-            a_1 = a_2;
-            f_1 = f_2;
-            ph_1 = ph_2;
+            }
         }
     }
 
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
 }
 
 // WC pass 1: z[q] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the chunked
-// layout (pad entries give 0).  The scalars of batch i+1 load while batch i runs.
+// layout (pad entries give 0).
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
@@ -322,60 +329,64 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
         const WaveRange R(wave_work, t, T, wave);
         __syncthreads();
-        if (R.e4 == 0) continue;
-        const int lim = kSE * R.e4, nb = (R.e4 + kGL - 1) / kGL;
-        int ix = R.index(mypos);
-        int a_0 = atom[ix];
-        float ph_0 = phi[ix];
-        for (int i = 0; i < nb; ++i) {
-            ix = R.index(kBatch * (i + 1) + mypos);
-            const int a_1 = atom[ix];
-            const float ph_1 = phi[ix];
-            const bool valid = kBatch * i + mypos < lim;
-            const int aoff = valid ? (a_0 - a0) * ROW : 0;
-            float p[kGL];
-#define LIFE_DOT2(J, CC, DV)                                                              \
-    q0 = fmaf(DV.x, yv[J][2 * CC + 0], q0);                                               \
-    q0 = fmaf(DV.y, yv[J][2 * CC + 1], q0);
+        if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
+        int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
+        int a_n = atom[ix];
+        float ph_n = phi[ix];
+#pragma unroll
+        for (int j = 0; j < kWaveVoxels; ++j) {
+            for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
+                const int m = min(kBatch, R.p[j + 1] - b);
+                const int a_c = a_n;
+                const float ph_c = ph_n;
+                int nxt = b + kBatch < R.p[j + 1] ? b + kBatch : R.p[j + 1];
+                nxt = nxt + mypos < R.p[kWaveVoxels] ? nxt + mypos : R.p[0];
+                a_n = atom[nxt];
+                ph_n = phi[nxt];
+                const bool valid = mypos < m;
+                const int aoff = valid ? (a_c - a0) * ROW : 0;
+                float p[kGL];
 #define LIFE_WCZ_STEP(K)                                                                  \
     {                                                                                     \
-        const int step = kGL * i + K;                                                     \
         const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
         float q0 = 0.f;                                                                   \
-        if (step < R.e4) {                                                                \
-            float2 dv[NC];                                                                \
-            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc)                             \
-                dv[cc] = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);           \
-            switch (R.slot(step)) {                                                       \
-            case 0: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(0, cc, dv[cc]) } break; \
-            case 1: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(1, cc, dv[cc]) } break; \
-            case 2: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(2, cc, dv[cc]) } break; \
-            default: _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) { LIFE_DOT2(3, cc, dv[cc]) } break; \
-            }                                                                             \
+        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
+            const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
+            q0 = fmaf(d.x, yv[j][2 * cc + 0], q0);                                        \
+            q0 = fmaf(d.y, yv[j][2 * cc + 1], q0);                                        \
         }                                                                                 \
         p[K] = q0;                                                                        \
     }
-            LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
-            LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
-            LIFE_WCZ_STEP(8) LIFE_WCZ_STEP(9) LIFE_WCZ_STEP(10) LIFE_WCZ_STEP(11)
-            LIFE_WCZ_STEP(12) LIFE_WCZ_STEP(13) LIFE_WCZ_STEP(14) LIFE_WCZ_STEP(15)
-#undef LIFE_WCZ_STEP
-#undef LIFE_DOT2
-            // transpose-reduce across the 16 lanes of each group (fixed butterfly):
-            // afterwards lane (g, l16) holds the full dot of step l16 = entry mypos
-#pragma unroll
-            for (int half = kGL / 2; half >= 1; half >>= 1) {
-                const bool hi = (l16 & half) != 0;
-#pragma unroll
-                for (int k = 0; k < half; ++k) {
-                    const float send = hi ? p[k] : p[k + half];
-                    const float keep = hi ? p[k + half] : p[k];
-                    p[k] = keep + __shfl_xor(send, half, 64);
+                if (m == kBatch) {
+                    LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
+                    LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
+                    LIFE_WCZ_STEP(8) LIFE_WCZ_STEP(9) LIFE_WCZ_STEP(10) LIFE_WCZ_STEP(11)
+                    LIFE_WCZ_STEP(12) LIFE_WCZ_STEP(13) LIFE_WCZ_STEP(14) LIFE_WCZ_STEP(15)
+                } else {
+                    const int ns = m / kSE;
+#define LIFE_WCZ_GSTEP(K) p[K] = 0.f; if (K < ns) LIFE_WCZ_STEP(K)
+                    LIFE_WCZ_GSTEP(0) LIFE_WCZ_GSTEP(1) LIFE_WCZ_GSTEP(2) LIFE_WCZ_GSTEP(3)
+                    LIFE_WCZ_GSTEP(4) LIFE_WCZ_GSTEP(5) LIFE_WCZ_GSTEP(6) LIFE_WCZ_GSTEP(7)
+                    LIFE_WCZ_GSTEP(8) LIFE_WCZ_GSTEP(9) LIFE_WCZ_GSTEP(10) LIFE_WCZ_GSTEP(11)
+                    LIFE_WCZ_GSTEP(12) LIFE_WCZ_GSTEP(13) LIFE_WCZ_GSTEP(14) LIFE_WCZ_GSTEP(15)
+#undef LIFE_WCZ_GSTEP
                 }
+#undef LIFE_WCZ_STEP
+                // transpose-reduce across the 16 lanes of each group (fixed butterfly):
+                // afterwards lane (g, l16) holds the full dot of step l16 = entry mypos
+#define LIFE_TR_STAGE(H)                                                                  \
+    {                                                                                     \
+        const bool hi = (l16 & H) != 0;                                                   \
+        _Pragma("unroll") for (int k = 0; k < H; ++k) {                                   \
+            const float send = hi ? p[k] : p[k + H];                                      \
+            const float keep = hi ? p[k + H] : p[k];                                      \
+            p[k] = keep + xor16<H>(send, l16);                                            \
+        }                                                                                 \
+    }
+                LIFE_TR_STAGE(8) LIFE_TR_STAGE(4) LIFE_TR_STAGE(2) LIFE_TR_STAGE(1)
+#undef LIFE_TR_STAGE
+                if (valid) z[b + mypos] = ph_c * p[0];
             }
-            if (valid) z[R.q0 + kBatch * i + mypos] = ph_0 * p[0];
-            a_0 = a_1;
-            ph_0 = ph_1;
         }
     }
 }
@@ -816,7 +827,7 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     if (st != LIFE_OK) return st;
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
-    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, cpos, wperm_c;
+    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, wperm_c;
     std::vector<int16_t> atom_c;
     std::vector<int32_t> fas_c;
     std::vector<float> phi_c;
@@ -850,29 +861,9 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
             tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
             cvox.resize((size_t)n_chunks * kChunkVoxels);
             life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), tptr.data(), cvox.data());
-            wwork.resize((size_t)n_chunks * tg.n_tiles * kChunkWaves * life::kWorkInts);
-            cpos.resize((size_t)d.nnz);
-            n_pad = life::chunk_layout(&d, tg, tptr.data(), cvox.data(), n_chunks, wwork.data(), cpos.data());
-            if (n_pad > life::kMaxNnz) return LIFE_ERANGE;
-            // pad entries: zero value, an atom of their tile, fascicle rank 0
-            atom_c.assign((size_t)n_pad, 0);
-            fas_c.assign((size_t)n_pad, 0);
-            phi_c.assign((size_t)n_pad, 0.f);
-            for (int c = 0; c < n_chunks; ++c)
-                for (int t = 0; t < tg.n_tiles; ++t)
-                    for (int w = 0; w < kChunkWaves; ++w) {
-                        const int32_t *ww = &wwork[((size_t)(c * tg.n_tiles + t) * kChunkWaves + w) * life::kWorkInts];
-                        for (int64_t q = ww[0]; q < ww[0] + life::kStepEntries * (int64_t)ww[4]; ++q)
-                            atom_c[(size_t)q] = (int16_t)(t * tg.tile_atoms);
-                    }
-            for (int64_t p = 0; p < d.nnz; ++p) {
-                const size_t q = (size_t)cpos[(size_t)p];
-                atom_c[q] = atom_v[(size_t)p];
-                fas_c[q] = fas_v[(size_t)p];
-                phi_c[q] = phi_v[(size_t)p];
-            }
-            wperm_c.resize((size_t)d.nnz);
-            for (int64_t j = 0; j < d.nnz; ++j) wperm_c[(size_t)j] = cpos[(size_t)wperm[(size_t)j]];
+            n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), atom_v.data(), fas_v.data(),
+                                         phi_v.data(), wperm.data(), wwork, atom_c, fas_c, phi_c, wperm_c);
+            if (n_pad < 0) return LIFE_ERANGE;
         }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;

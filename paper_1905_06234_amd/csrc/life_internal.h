@@ -1,6 +1,8 @@
 // Internal declarations shared by the host plan builder and the device code.
 #pragma once
 
+#include <vector>
+
 #include "life.h"
 
 namespace life {
@@ -58,5 +60,14 @@ constexpr int kStepEntries = 4;
 constexpr int kWorkInts = 5;
 int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
                      int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
+
+// The padded arrays of the chunked layout from the canonical DSC-order arrays:
+// pad entries get value 0, an atom of their tile and fascicle rank 0;
+// wc_perm_c[j] = padded position of WC slot j.  Returns the padded length, or -1
+// if it exceeds the 32-bit position limit.
+int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
+                       const int32_t *chunk_vox, const int16_t *atom_v, const int32_t *fas_v, const float *phi_v,
+                       const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
+                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &wc_perm_c);
 
 }  // namespace life

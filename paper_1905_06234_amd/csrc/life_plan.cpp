@@ -212,6 +212,37 @@ int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile
     return q;
 }
 
+int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
+                       const int32_t *chunk_vox, const int16_t *atom_v, const int32_t *fas_v, const float *phi_v,
+                       const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
+                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &wc_perm_c)
+{
+    const int T = tg.n_tiles;
+    wave_work.assign((size_t)n_chunks * T * kChunkWaves * kWorkInts, 0);
+    std::vector<int32_t> cpos((size_t)d->nnz);
+    const int64_t n_pad = chunk_layout(d, tg, tile_ptr, chunk_vox, n_chunks, wave_work.data(), cpos.data());
+    if (n_pad > kMaxNnz) return -1;
+    atom_c.assign((size_t)n_pad, 0);
+    fas_c.assign((size_t)n_pad, 0);
+    phi_c.assign((size_t)n_pad, 0.f);
+    for (int c = 0; c < n_chunks; ++c)
+        for (int t = 0; t < T; ++t)
+            for (int w = 0; w < kChunkWaves; ++w) {
+                const int32_t *ww = &wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
+                for (int64_t q = ww[0]; q < ww[0] + kStepEntries * (int64_t)ww[kWaveVoxels]; ++q)
+                    atom_c[(size_t)q] = static_cast<int16_t>(t * tg.tile_atoms);
+            }
+    for (int64_t p = 0; p < d->nnz; ++p) {
+        const size_t q = (size_t)cpos[(size_t)p];
+        atom_c[q] = atom_v[p];
+        fas_c[q] = fas_v[p];
+        phi_c[q] = phi_v[p];
+    }
+    wc_perm_c.resize((size_t)d->nnz);
+    for (int64_t j = 0; j < d->nnz; ++j) wc_perm_c[(size_t)j] = cpos[(size_t)wc_perm[j]];
+    return n_pad;
+}
+
 }  // namespace life
 
 extern "C" life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
