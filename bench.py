@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--config", default="full", choices=["tiny", "mid", "full"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--voxel-order", default="morton", choices=["morton", "index"],
+                    help="voxel processing order of the plan: Morton order of the grid coordinates, or voxel index")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -108,7 +110,7 @@ def main():
     c = synth.make(args.config)
     log(f"generated {args.config}: nnz={c.nnz} Nv={c.n_voxels} Nf={c.n_fascicles} ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    plan = life.Plan.from_connectome(c)
+    plan = life.Plan.from_connectome(c, morton=args.voxel_order == "morton")
     plan_ms = (time.perf_counter() - t0) * 1e3
     log(f"plan built in {plan_ms:.0f} ms")
     d = plan.dims
@@ -174,6 +176,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.config} synthetic connectome", "n_theta": d.n_theta, "n_atoms": d.n_atoms,
                    "n_voxels": d.n_voxels, "n_fascicles": d.n_fascicles, "nnz": d.nnz,
+                   "voxel_order": args.voxel_order,
                    "step": "one SBB-NNLS iteration (2 DSC + 1 or 2 WC + glue)"},
         "pair_kernel_nnz_per_s": round(d.nnz / ((t_dsc + t_wc) / 1e3), 1) if t_dsc + t_wc > 0 else None,
         "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},

@@ -95,24 +95,28 @@ const char *life_status_str(life_status s);
 /* Restructuring on the host only (no device touched): the data-restructuring
  * step of Sec. 4.1 ("Data Restructuring": voxel-based for DSC; fiber-based,
  * i.e. by fascicle, for WC) as two permutations with their segment offsets.
- * Fascicles are processed in a locality order: by the mean index of the voxels
- * they cross (ties and empty fascicles by fascicle index, empty ones last), so
- * that fascicles handled together touch nearby voxels.
+ * Voxels are processed in a locality order: voxel index order, or, when grid
+ * coordinates are given, the Morton (Z-order) sequence of the coordinates (ties
+ * by index).  Fascicles are ranked by the mean processing position of the voxels
+ * they cross (ties by fascicle index, empty fascicles last), so that fascicles
+ * handled together touch nearby voxels.
  *   atom, voxel, fascicle: host, nnz entries each (input COO order).
+ *   voxel_xyz (host, 3*n_voxels, optional): non-negative (x, y, z) grid
+ *                                   coordinates of each voxel, or NULL.
  *   dsc_perm  (host, nnz):          input positions in DSC order, the total order
  *                                   (voxel, atom, fascicle, input position).
  *   vox_ptr   (host, n_voxels+1):   voxel v owns DSC positions [vox_ptr[v], vox_ptr[v+1]).
  *   fas_rank  (host, n_fascicles):  processing rank of each fascicle (a permutation).
  *   wc_perm   (host, nnz):          for WC slot j, its position in the DSC order; WC
- *                                   slots follow (fas_rank[fascicle], voxel, atom,
- *                                   input position).
+ *                                   slots follow (fas_rank[fascicle], voxel position,
+ *                                   atom, fascicle, input position).
  *   fas_ptr   (host, n_fascicles+1): the fascicle of rank r owns WC slots
  *                                   [fas_ptr[r], fas_ptr[r+1]).
  * Any output may be NULL (not written).  Errors: LIFE_EINVAL (dims or a needed
- * pointer NULL), LIFE_ERANGE (an index out of range), LIFE_ENOMEM. */
+ * pointer NULL), LIFE_ERANGE (an index or a coordinate out of range), LIFE_ENOMEM. */
 life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
-                           const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                           int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
+                           const int32_t *fascicle, const int16_t *voxel_xyz, int32_t *dsc_perm,
+                           int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
 
 /* Build a plan on the current HIP device from host COO arrays (Sec. 2.2 Phi
  * vectors; restructuring of Sec. 4.1 done once and amortized over the
@@ -123,6 +127,15 @@ life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int
  * LIFE_ENOMEM, LIFE_EDEVICE. */
 life_status life_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
                       const int32_t *fascicle, const float *phi, life_plan_t *out);
+
+/* life_plan with the voxels' grid coordinates (host, 3*n_voxels, non-negative;
+ * NULL = life_plan): the plan then processes voxels in Morton order, so each
+ * 64-voxel work chunk is a compact block and the WC gathers stay local (see
+ * life_plan_host).  Results are the same products; only summation orders and
+ * speed differ.  Errors: as life_plan; LIFE_ERANGE for a negative coordinate. */
+life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                         const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                         life_plan_t *out);
 
 /* Release a plan and its device memory (synchronizes the device first).
  * NULL is accepted and ignored. */

@@ -166,6 +166,19 @@ struct WaveRange {
 #pragma unroll
         for (int j = 1; j <= kWaveVoxels; ++j) p[j] = q0 + kSE * uni(ww[j]);
     }
+    // start of the batch that follows the batch starting at b (p[kWaveVoxels] = none):
+    // the next 64 entries of the same slot, else the start of the next non-empty slot
+    __device__ __forceinline__ int next(int b) const
+    {
+        if (b >= p[kWaveVoxels]) return p[kWaveVoxels];
+        const int e = b < p[1] ? p[1] : b < p[2] ? p[2] : b < p[3] ? p[3] : p[4];
+        return b + kBatch < e ? b + kBatch : e;
+    }
+    // in-bounds entry index for this lane in the batch starting at b (clamped)
+    __device__ __forceinline__ int entry(int b, int mypos) const
+    {
+        return b + mypos < p[kWaveVoxels] ? b + mypos : p[0];
+    }
 };
 
 // Lane layout of the chunked kernels: a wave is kSE groups of kGL = 16 lanes; at
@@ -210,22 +223,31 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         const WaveRange R(wave_work, t, T, wave);
         __syncthreads();
         if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
-        // scalars of the first batch of the wave's range
-        int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
-        int a_n = atom[ix], f_n = fas[ix];
-        float ph_n = phi[ix];
+        // two-stage prefetch over batch starts: the scalars of batch i+2 and the
+        // w gather of batch i+1 are in flight while batch i is computed
+        int bq = R.next(R.p[0]);
+        int ix = R.entry(R.p[0], mypos);
+        int a_0 = atom[ix], f_0 = fas[ix];
+        float ph_0 = phi[ix];
+        ix = R.entry(bq, mypos);
+        int a_1 = atom[ix], f_1 = fas[ix];
+        float ph_1 = phi[ix];
+        float w_0 = w[f_0];
 #pragma unroll
         for (int j = 0; j < kWaveVoxels; ++j) {
             for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
                 const int m = min(kBatch, R.p[j + 1] - b);
-                const int a_c = a_n;
-                const float ph_c = ph_n, w_c = w[f_n];
-                // prefetch the next batch: same slot, else the first batch of a later slot
-                int nxt = b + kBatch < R.p[j + 1] ? b + kBatch : R.p[j + 1];
-                nxt = nxt + mypos < R.p[kWaveVoxels] ? nxt + mypos : R.p[0];
-                a_n = atom[nxt];
-                f_n = fas[nxt];
-                ph_n = phi[nxt];
+                const int a_c = a_0;
+                const float ph_c = ph_0, w_c = w_0;
+                const float w_1 = w[f_1];
+                bq = R.next(bq);
+                ix = R.entry(bq, mypos);
+                a_0 = a_1;
+                ph_0 = ph_1;
+                w_0 = w_1;
+                a_1 = atom[ix];
+                f_1 = fas[ix];
+                ph_1 = phi[ix];
                 const bool valid = mypos < m;
                 const int aoff = valid ? (a_c - a0) * ROW : 0;
                 const float s = valid ? ph_c * w_c : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
@@ -290,13 +312,16 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     if (part) block_sum_store<kWG>(sq, part);
 }
 
-// WC pass 1: z[q] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the chunked
-// layout (pad entries give 0).
+// WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the
+// chunked layout (pad entries give 0).  z_pos keeps each chunk's values inside the
+// chunk's own range, in WC order, so pass 2 reads one fascicle's values in a chunk
+// as one contiguous run.
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
                                                    const float *__restrict__ phi,
+                                                   const int32_t *__restrict__ z_pos,
                                                    const float *__restrict__ D,
                                                    const float *__restrict__ y,
                                                    float *__restrict__ z, int nth, int na, int T, int TA,
@@ -385,7 +410,7 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
     }
                 LIFE_TR_STAGE(8) LIFE_TR_STAGE(4) LIFE_TR_STAGE(2) LIFE_TR_STAGE(1)
 #undef LIFE_TR_STAGE
-                if (valid) z[b + mypos] = ph_c * p[0];
+                if (valid) z[z_pos[b + mypos]] = ph_c * p[0];
             }
         }
     }
@@ -499,7 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
 }
 
 // WC pass 2: g[out(r)] = sum_{j in seg(r)} z[wperm[j]] for the fascicle of rank r
-// (16 lanes per fascicle, fixed tree); out(r) = gmap[r] (caller order) or r.
+// (16 lanes per fascicle; each lane keeps 4 index loads and 4 gathers in flight;
+// fixed summation tree); out(r) = gmap[r] (caller order) or r.
 __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
                                                     const int32_t *__restrict__ wperm,
                                                     const float *__restrict__ z,
@@ -512,8 +538,19 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
     const int f = blockIdx.x * kFasPerBlock + threadIdx.x / kFasLanes;
     float s = 0.f;
     if (f < nf) {
-        const int end = fptr[f + 1];
-        for (int j = fptr[f] + lane; j < end; j += kFasLanes) s += z[wperm[j]];
+        const int beg = fptr[f], end = fptr[f + 1];
+        for (int j = beg + lane; j < end; j += 4 * kFasLanes) {
+            const int j1 = j + kFasLanes, j2 = j + 2 * kFasLanes, j3 = j + 3 * kFasLanes;
+            const int i0 = wperm[j];
+            const int i1 = wperm[j1 < end ? j1 : j];
+            const int i2 = wperm[j2 < end ? j2 : j];
+            const int i3 = wperm[j3 < end ? j3 : j];
+            const float z0 = z[i0];
+            const float z1 = j1 < end ? z[i1] : 0.f;
+            const float z2 = j2 < end ? z[i2] : 0.f;
+            const float z3 = j3 < end ? z[i3] : 0.f;
+            s += (z0 + z1) + (z2 + z3);
+        }
     }
 #pragma unroll
     for (int o = kFasLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kFasLanes);
@@ -611,7 +648,8 @@ struct life_plan_s {
     int16_t *atom_c = nullptr;    // [n_pad]
     int32_t *fas_c = nullptr;     // [n_pad]
     float *phi_c = nullptr;       // [n_pad]
-    int32_t *wc_perm_c = nullptr; // [nnz] padded position of each WC slot
+    int32_t *z_pos = nullptr;     // [n_pad] z position of each padded entry
+    int32_t *wc_perm_z = nullptr; // [nnz] z position of each WC slot
     // fascicles are processed in rank order (fas_v holds ranks)
     int32_t *fas_rank = nullptr;  // [Nf] rank of each fascicle
     int32_t *fas_ext = nullptr;   // [Nf] fascicle of each rank
@@ -658,7 +696,7 @@ hipError_t dalloc(T **p, int64_t n)
 void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->wave_work, p->atom_c, p->fas_c,
-                    p->phi_c, p->wc_perm_c, p->fas_rank, p->fas_ext,
+                    p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
                     p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->part};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -781,7 +819,7 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
             const size_t lds = tile_lds_bytes(p);
             st = launch(p, kind, s, [&] {
                 LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
-                                                                               p->phi_c, D, y, p->z, nth,
+                                                                               p->phi_c, p->z_pos, D, y, p->z, nth,
                                                                                p->dims.n_atoms, p->tile.n_tiles,
                                                                                p->tile.tile_atoms, vec_tile(p, D),
                                                                                gate))
@@ -798,7 +836,7 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
         st = launch(p, gate ? LIFE_K_WC_SUM_EVEN : LIFE_K_WC_SUM, s, [&] {
-            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_c : p->wc_perm, p->z, gmap, g,
+            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_z : p->wc_perm, p->z, gmap, g,
                                              part, nf, gate);
         });
     }
@@ -821,20 +859,25 @@ life_status enqueue_gather(life_plan_s *p, const float *w, hipStream_t s)
 extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
                                  const int32_t *fascicle, const float *phi, life_plan_t *out)
 {
+    return life_plan_ex(dims, atom, voxel, fascicle, phi, nullptr, out);
+}
+
+extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                                    const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                                    life_plan_t *out)
+{
     if (!out) return LIFE_EINVAL;
     *out = nullptr;
     life_status st = life::validate_dims(dims);
     if (st != LIFE_OK) return st;
+    if ((st = life::validate_coords(dims, voxel_xyz)) != LIFE_OK) return st;
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
-    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, wperm_c;
-    std::vector<int16_t> atom_c;
-    std::vector<int32_t> fas_c;
-    std::vector<float> phi_c;
+    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, ppos, pvox, vdsc;
+    std::vector<int16_t> atom_v, atom_c;
+    std::vector<int32_t> fas_v, fas_c;
+    std::vector<float> phi_v, phi_c;
     int64_t n_pad = 0;
-    std::vector<int16_t> atom_v;
-    std::vector<int32_t> fas_v;
-    std::vector<float> phi_v;
     const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
     const int n_chunks = tg.row_floats > 0 ? cdiv(d.n_voxels, kChunkVoxels) : 0;
     try {
@@ -844,25 +887,31 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
         fptr.resize((size_t)d.n_fascicles + 1);
         rank.resize((size_t)d.n_fascicles);
         ext.resize((size_t)d.n_fascicles);
-        st = life::plan_host(&d, atom, voxel, fascicle, perm.data(), vptr.data(), rank.data(), wperm.data(),
-                             fptr.data());
+        ppos.resize((size_t)d.n_voxels);
+        pvox.resize((size_t)d.n_voxels);
+        life::voxel_order(&d, voxel_xyz, ppos.data(), pvox.data());
+        st = life::plan_host(&d, atom, voxel, fascicle, voxel_xyz ? ppos.data() : nullptr, perm.data(), vptr.data(),
+                             rank.data(), wperm.data(), fptr.data());
         if (st != LIFE_OK) return st;
         for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
         atom_v.resize((size_t)d.nnz);
         fas_v.resize((size_t)d.nnz);
         phi_v.resize((size_t)d.nnz);
+        vdsc.resize((size_t)d.nnz);
         for (int64_t p = 0; p < d.nnz; ++p) {
             const int32_t c = perm[(size_t)p];
             atom_v[(size_t)p] = atom[c];
             fas_v[(size_t)p] = rank[(size_t)fascicle[c]];
             phi_v[(size_t)p] = phi[c];
+            vdsc[(size_t)p] = voxel[c];
         }
         if (n_chunks > 0) {
             tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
             cvox.resize((size_t)n_chunks * kChunkVoxels);
-            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), tptr.data(), cvox.data());
-            n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), atom_v.data(), fas_v.data(),
-                                         phi_v.data(), wperm.data(), wwork, atom_c, fas_c, phi_c, wperm_c);
+            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), pvox.data(), tptr.data(), cvox.data());
+            n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), ppos.data(), atom_v.data(),
+                                         fas_v.data(), phi_v.data(), vdsc.data(), wperm.data(), wwork, atom_c,
+                                         fas_c, phi_c, zpos, wperm_z);
             if (n_pad < 0) return LIFE_ERANGE;
         }
     } catch (const std::bad_alloc &) {
@@ -895,7 +944,8 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     chk(dalloc(&p->atom_c, n_pad));
     chk(dalloc(&p->fas_c, n_pad));
     chk(dalloc(&p->phi_c, n_pad));
-    chk(dalloc(&p->wc_perm_c, (int64_t)wperm_c.size()));
+    chk(dalloc(&p->z_pos, (int64_t)zpos.size()));
+    chk(dalloc(&p->wc_perm_z, (int64_t)wperm_z.size()));
     chk(dalloc(&p->fas_rank, d.n_fascicles));
     chk(dalloc(&p->fas_ext, d.n_fascicles));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
@@ -925,7 +975,8 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     up(p->atom_c, atom_c.data(), sizeof(int16_t) * atom_c.size());
     up(p->fas_c, fas_c.data(), sizeof(int32_t) * fas_c.size());
     up(p->phi_c, phi_c.data(), sizeof(float) * phi_c.size());
-    up(p->wc_perm_c, wperm_c.data(), sizeof(int32_t) * wperm_c.size());
+    up(p->z_pos, zpos.data(), sizeof(int32_t) * zpos.size());
+    up(p->wc_perm_z, wperm_z.data(), sizeof(int32_t) * wperm_z.size());
     up(p->fas_rank, rank.data(), sizeof(int32_t) * rank.size());
     up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());

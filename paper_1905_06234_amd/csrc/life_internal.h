@@ -13,19 +13,24 @@ constexpr int64_t kMaxNnz = 2147483646;  // int32 positions, with room for nnz i
 life_status validate_dims(const life_dims *d);
 life_status validate_indices(const life_dims *d, const int16_t *atom, const int32_t *voxel,
                              const int32_t *fascicle);
-life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel,
-                      const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
+life_status validate_coords(const life_dims *d, const int16_t *voxel_xyz);
 
-}  // namespace life
+// Voxel processing order: voxel id order, or, given grid coordinates, the Morton
+// (Z-order) sequence of the coordinates (ties by id), so that consecutive voxels
+// form compact blocks.  proc_pos[v] = position of voxel v; proc_vox[k] = voxel at k.
+void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int32_t *proc_pos, int32_t *proc_vox);
 
-namespace life {
+// Host restructuring (see life_plan_host in life.h); proc_pos may be NULL (id order).
+life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
+                      const int32_t *proc_pos, int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank,
+                      int32_t *wc_perm, int32_t *fas_ptr);
 
 // Work decomposition of the chunked (LDS-tiled) kernels, computed on the host.
 //   The dictionary is staged in shared memory one atom tile at a time: n_tiles
 //   tiles of tile_atoms atoms, each row padded to row_floats (a multiple of 32).
-//   Voxels are cut into chunks of kChunkVoxels consecutive voxels; a chunk is one
-//   workgroup of kChunkWaves waves and each wave owns up to kWaveVoxels voxels.
+//   Voxels are cut into chunks of kChunkVoxels consecutive voxels of the
+//   processing order; a chunk is one workgroup of kChunkWaves waves and each
+//   wave owns up to kWaveVoxels voxels.
 constexpr int kChunkWaves = 16;
 constexpr int kWaveVoxels = 4;
 constexpr int kChunkVoxels = kChunkWaves * kWaveVoxels;
@@ -45,29 +50,33 @@ TileGeom tile_geometry(int n_theta, int n_atoms);
 // chunk_vox[c*kChunkVoxels + wave*kWaveVoxels + j]: voxel owned by slot j of a wave in chunk c
 // (-1 = empty), balanced inside each chunk by longest-processing-time assignment.
 void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                int32_t *tile_ptr, int32_t *chunk_vox);
+                const int32_t *proc_vox, int32_t *tile_ptr, int32_t *chunk_vox);
 
 // Chunked layout: for every (chunk c, tile t, wave w) one contiguous range of the
 // padded arrays holds the tile-t sub-ranges of the wave's voxel slots j = 0..3,
 // each padded with zero-valued entries to a multiple of kStepEntries (one step of
-// the wave's lane groups never mixes voxels).
+// the wave's lane groups never mixes voxels); chunks are laid out one after the
+// other.
 // wave_work[((c*T + t)*kChunkWaves + w)*kWorkInts + k]:
 //   k = 0: first position of the range; k = 1..4: cumulative step counts E1..E4
 //   (slot j owns steps [E_j, E_{j+1}), E_0 = 0; kStepEntries entries per step).
 constexpr int kStepEntries = 4;
-// chunk_pos[p] = padded position of canonical DSC position p.  Returns the
-// padded length.  pad_tile[q] = tile of padded position q (for pad entries).
 constexpr int kWorkInts = 5;
 int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
                      int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
 
 // The padded arrays of the chunked layout from the canonical DSC-order arrays:
-// pad entries get value 0, an atom of their tile and fascicle rank 0;
-// wc_perm_c[j] = padded position of WC slot j.  Returns the padded length, or -1
-// if it exceeds the 32-bit position limit.
+// pad entries get value 0, an atom of their tile and fascicle rank 0.  The WC
+// pass-1 output z uses its own order inside each chunk's range: the chunk's
+// entries in WC order (so one fascicle's entries in one chunk are adjacent),
+// then its pad entries.  z_pos[q] = z position of padded entry q;
+// wc_perm_z[j] = z position of WC slot j.  Returns the padded length, or -1 if it
+// exceeds the 32-bit position limit.
 int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
-                       const int32_t *chunk_vox, const int16_t *atom_v, const int32_t *fas_v, const float *phi_v,
+                       const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
+                       const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
                        const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
-                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &wc_perm_c);
+                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
+                       std::vector<int32_t> &wc_perm_z);
 
 }  // namespace life

@@ -7,8 +7,11 @@
 // paper sets aside and this library uses for WC because it needs no atomics -
 // by fiber (fascicle).  Both orders here are total orders, so a plan is unique:
 //   DSC order: (voxel, atom, fascicle, input position)
-//   WC order : (fascicle, voxel, atom, input position)
-// They are built with stable LSD counting sorts, O(nnz + N) per key.
+//   WC order : (fascicle rank, voxel position, atom, fascicle, input position)
+// where the voxel position is the voxel's place in the processing order (id
+// order, or Morton order of its grid coordinates when they are given) and the
+// fascicle rank orders fascicles by the mean position of their voxels.  They are
+// built with stable LSD counting sorts, O(nnz + N) per key.
 //
 // Pure C++17: no HIP, so it can be checked on the host alone.
 #include "life_internal.h"
@@ -45,6 +48,14 @@ life_status validate_indices(const life_dims *d, const int16_t *atom, const int3
     return bad ? LIFE_ERANGE : LIFE_OK;
 }
 
+life_status validate_coords(const life_dims *d, const int16_t *voxel_xyz)
+{
+    if (!voxel_xyz) return LIFE_OK;
+    for (int64_t i = 0; i < 3 * (int64_t)d->n_voxels; ++i)
+        if (voxel_xyz[i] < 0) return LIFE_ERANGE;
+    return LIFE_OK;
+}
+
 namespace {
 
 // Stable counting sort of the items in `in` by key(item) in [0, nkeys).
@@ -68,15 +79,26 @@ void segment_offsets(const int32_t *keys_in_order, int64_t n, int32_t nkeys, int
     }
 }
 
-}  // namespace
+// Morton (Z-order) key: bit b of x, y, z goes to bit 3b, 3b+1, 3b+2.
+uint64_t morton_key(const int16_t *c)
+{
+    uint64_t key = 0;
+    for (int b = 0; b < 16; ++b)
+        for (int axis = 0; axis < 3; ++axis)
+            key |= (uint64_t)(((uint16_t)c[axis] >> b) & 1u) << (3 * b + axis);
+    return key;
+}
 
-void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fascicle, int32_t *rank)
+// Fascicle rank: fascicles in order of the mean processing position of their
+// voxels (empty fascicles last, ties by index).
+void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fascicle, const int32_t *proc_pos,
+                    int32_t *rank)
 {
     const int32_t nf = d->n_fascicles;
     std::vector<double> sum(static_cast<size_t>(nf), 0.0);
     std::vector<int64_t> cnt(static_cast<size_t>(nf), 0);
     for (int64_t c = 0; c < d->nnz; ++c) {
-        sum[fascicle[c]] += voxel[c];
+        sum[fascicle[c]] += proc_pos ? proc_pos[voxel[c]] : voxel[c];
         ++cnt[fascicle[c]];
     }
     std::vector<double> key(static_cast<size_t>(nf));
@@ -87,9 +109,29 @@ void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fas
     for (int32_t r = 0; r < nf; ++r) rank[order[r]] = r;
 }
 
-life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel,
-                      const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
+}  // namespace
+
+void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int32_t *proc_pos, int32_t *proc_vox)
+{
+    const int32_t nv = d->n_voxels;
+    std::vector<int32_t> order(static_cast<size_t>(nv));
+    for (int32_t v = 0; v < nv; ++v) order[v] = v;
+    if (voxel_xyz) {
+        std::vector<uint64_t> key(static_cast<size_t>(nv));
+        for (int32_t v = 0; v < nv; ++v) {
+            key[v] = morton_key(voxel_xyz + 3 * (int64_t)v);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
+    for (int32_t k = 0; k < nv; ++k) {
+        if (proc_vox) proc_vox[k] = order[k];
+        if (proc_pos) proc_pos[order[k]] = k;
+    }
+}
+
+life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
+                      const int32_t *proc_pos, int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank,
+                      int32_t *wc_perm, int32_t *fas_ptr)
 {
     life_status st = validate_dims(d);
     if (st != LIFE_OK) return st;
@@ -111,16 +153,21 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
             segment_offsets(keys.data(), n, d->n_voxels, vox_ptr);
         }
         std::vector<int32_t> rank(static_cast<size_t>(d->n_fascicles));
-        fascicle_ranks(d, voxel, fascicle, rank.data());
+        fascicle_ranks(d, voxel, fascicle, proc_pos, rank.data());
         if (fas_rank && d->n_fascicles)
             std::memcpy(fas_rank, rank.data(), sizeof(int32_t) * static_cast<size_t>(d->n_fascicles));
         if (wc_perm || fas_ptr) {
-            // Stable sort of DSC positions by fascicle rank: the DSC order already ranks
-            // (voxel, atom, input position), so ties come out in exactly that order.
-            for (int64_t p = 0; p < n; ++p) a[p] = static_cast<int32_t>(p);
+            // Stable sorts of DSC positions: by voxel position (a no-op in id order),
+            // then by fascicle rank; the DSC order supplies (atom, fascicle, position).
             std::vector<int32_t> w(static_cast<size_t>(n));
-            counting_sort(a.data(), w.data(), n, d->n_fascicles,
-                          [&](int32_t p) { return rank[fascicle[b[p]]]; }, cnt);
+            for (int64_t p = 0; p < n; ++p) a[p] = static_cast<int32_t>(p);
+            if (proc_pos) {
+                counting_sort(a.data(), w.data(), n, d->n_voxels, [&](int32_t p) { return proc_pos[voxel[b[p]]]; },
+                              cnt);
+                std::swap(a, w);
+            }
+            counting_sort(a.data(), w.data(), n, d->n_fascicles, [&](int32_t p) { return rank[fascicle[b[p]]]; },
+                          cnt);
             if (fas_ptr) {
                 std::vector<int32_t> keys(static_cast<size_t>(n));
                 for (int64_t j = 0; j < n; ++j) keys[j] = rank[fascicle[b[w[j]]]];
@@ -149,7 +196,7 @@ TileGeom tile_geometry(int n_theta, int n_atoms)
 }
 
 void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                int32_t *tile_ptr, int32_t *chunk_vox)
+                const int32_t *proc_vox, int32_t *tile_ptr, int32_t *chunk_vox)
 {
     const int nv = d->n_voxels, T = tg.n_tiles;
     for (int v = 0; v < nv; ++v) {
@@ -165,10 +212,10 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
     const int nchunks = (nv + kChunkVoxels - 1) / kChunkVoxels;
     std::vector<int> ids;
     for (int c = 0; c < nchunks; ++c) {
-        const int v0 = c * kChunkVoxels, v1 = std::min(nv, v0 + kChunkVoxels);
+        const int k0 = c * kChunkVoxels, k1 = std::min(nv, k0 + kChunkVoxels);
         ids.clear();
-        for (int v = v0; v < v1; ++v) ids.push_back(v);
-        // longest first; ties by voxel id so the plan is unique
+        for (int k = k0; k < k1; ++k) ids.push_back(proc_vox ? proc_vox[k] : k);
+        // longest first; ties keep processing order so the plan is unique
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
             return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
         });
@@ -189,13 +236,14 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
 int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
                      int n_chunks, int32_t *wave_work, int32_t *chunk_pos)
 {
+    (void)d;
     const int T = tg.n_tiles;
     int64_t q = 0;
     for (int c = 0; c < n_chunks; ++c)
         for (int t = 0; t < T; ++t)
             for (int w = 0; w < kChunkWaves; ++w) {
                 int32_t *ww = wave_work + ((int64_t)(c * T + t) * kChunkWaves + w) * kWorkInts;
-                ww[0] = static_cast<int32_t>(q);
+                ww[0] = static_cast<int32_t>(std::min<int64_t>(q, kMaxNnz));
                 int steps = 0;
                 for (int j = 0; j < kWaveVoxels; ++j) {
                     const int v = chunk_vox[(int64_t)c * kChunkVoxels + w * kWaveVoxels + j];
@@ -213,9 +261,11 @@ int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile
 }
 
 int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
-                       const int32_t *chunk_vox, const int16_t *atom_v, const int32_t *fas_v, const float *phi_v,
+                       const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
+                       const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
                        const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
-                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &wc_perm_c)
+                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
+                       std::vector<int32_t> &wc_perm_z)
 {
     const int T = tg.n_tiles;
     wave_work.assign((size_t)n_chunks * T * kChunkWaves * kWorkInts, 0);
@@ -238,18 +288,50 @@ int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, con
         fas_c[q] = fas_v[p];
         phi_c[q] = phi_v[p];
     }
-    wc_perm_c.resize((size_t)d->nnz);
-    for (int64_t j = 0; j < d->nnz; ++j) wc_perm_c[(size_t)j] = cpos[(size_t)wc_perm[j]];
+    // z order: inside each chunk's range, its entries in WC order, then its pads
+    std::vector<int64_t> next((size_t)n_chunks + 1);
+    for (int c = 0; c < n_chunks; ++c) next[c] = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];
+    next[n_chunks] = n_pad;
+    const std::vector<int64_t> chunk_end(next.begin() + 1, next.end());
+    z_pos.assign((size_t)n_pad, -1);
+    wc_perm_z.resize((size_t)d->nnz);
+    for (int64_t j = 0; j < d->nnz; ++j) {
+        const int32_t p = wc_perm[j];
+        const int32_t v = voxel_of_dsc[p];
+        const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
+        const int32_t zp = static_cast<int32_t>(next[c]++);
+        z_pos[(size_t)cpos[(size_t)p]] = zp;
+        wc_perm_z[(size_t)j] = zp;
+    }
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t cb = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];
+        for (int64_t q = cb; q < chunk_end[c]; ++q)
+            if (z_pos[(size_t)q] < 0) z_pos[(size_t)q] = static_cast<int32_t>(next[c]++);
+        if (next[c] != chunk_end[c]) return -1;   // layout inconsistency (cannot happen)
+    }
     return n_pad;
 }
 
 }  // namespace life
 
 extern "C" life_status life_plan_host(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
-                                      const int32_t *fascicle, int32_t *dsc_perm, int32_t *vox_ptr,
-                                      int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
+                                      const int32_t *fascicle, const int16_t *voxel_xyz, int32_t *dsc_perm,
+                                      int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
 {
-    return life::plan_host(dims, atom, voxel, fascicle, dsc_perm, vox_ptr, fas_rank, wc_perm, fas_ptr);
+    life_status st = life::validate_dims(dims);
+    if (st != LIFE_OK) return st;
+    if ((st = life::validate_coords(dims, voxel_xyz)) != LIFE_OK) return st;
+    try {
+        std::vector<int32_t> pos;
+        if (voxel_xyz) {
+            pos.resize((size_t)dims->n_voxels);
+            life::voxel_order(dims, voxel_xyz, pos.data(), nullptr);
+        }
+        return life::plan_host(dims, atom, voxel, fascicle, voxel_xyz ? pos.data() : nullptr, dsc_perm, vox_ptr,
+                               fas_rank, wc_perm, fas_ptr);
+    } catch (const std::bad_alloc &) {
+        return LIFE_ENOMEM;
+    }
 }
 
 extern "C" const char *life_status_str(life_status s)

@@ -44,8 +44,9 @@ _lib = None
 _P = ctypes.c_void_p
 _SIGS = {
     "life_status_str": (ctypes.c_char_p, [ctypes.c_int]),
-    "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, _P]),
+    "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "life_plan": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "life_plan_ex": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "life_plan_destroy": (ctypes.c_int, [_P]),
     "life_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(Dims)]),
     "life_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
@@ -90,17 +91,27 @@ def _coo(atom, voxel, fascicle):
     return atom, voxel, fascicle
 
 
-def plan_host(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle
-              ) -> Dict[str, np.ndarray]:
+def _xyz(voxel_xyz, n_voxels: int):
+    if voxel_xyz is None:
+        return None
+    xyz = np.ascontiguousarray(voxel_xyz, dtype=np.int16)
+    if xyz.shape != (max(n_voxels, 0), 3):
+        raise ValueError("voxel_xyz must have shape (n_voxels, 3)")
+    return xyz
+
+
+def plan_host(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle,
+              voxel_xyz=None) -> Dict[str, np.ndarray]:
     """Host-only restructuring (life_plan_host): permutations and segment offsets."""
     atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+    xyz = _xyz(voxel_xyz, n_voxels)
     nnz = atom.shape[0]
     d = Dims(n_theta, n_atoms, n_voxels, n_fascicles, nnz)
     out = {"dsc_perm": np.empty(nnz, np.int32), "vox_ptr": np.empty(max(n_voxels, 0) + 1, np.int32),
            "fas_rank": np.empty(max(n_fascicles, 0), np.int32), "wc_perm": np.empty(nnz, np.int32),
            "fas_ptr": np.empty(max(n_fascicles, 0) + 1, np.int32)}
     _check("life_plan_host", load().life_plan_host(ctypes.byref(d), _np_ptr(atom), _np_ptr(voxel),
-                                                   _np_ptr(fascicle), _np_ptr(out["dsc_perm"]),
+                                                   _np_ptr(fascicle), _np_ptr(xyz), _np_ptr(out["dsc_perm"]),
                                                    _np_ptr(out["vox_ptr"]), _np_ptr(out["fas_rank"]),
                                                    _np_ptr(out["wc_perm"]), _np_ptr(out["fas_ptr"])))
     return out
@@ -149,21 +160,31 @@ class Plan:
     """A restructured Phi on one device (life_plan); owns its device memory."""
 
     def __init__(self, n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int,
-                 atom, voxel, fascicle, phi):
+                 atom, voxel, fascicle, phi, voxel_xyz=None):
+        """voxel_xyz: optional (n_voxels, 3) grid coordinates; given, voxels are
+        processed in Morton order (life_plan_ex)."""
         atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+        xyz = _xyz(voxel_xyz, n_voxels)
         phi = np.ascontiguousarray(phi, dtype=np.float32)
         if phi.shape != atom.shape:
             raise ValueError("phi must have one value per nonzero")
         self.dims = Dims(n_theta, n_atoms, n_voxels, n_fascicles, atom.shape[0])
         self._h = ctypes.c_void_p()
         lib = load()
-        _check("life_plan", lib.life_plan(ctypes.byref(self.dims), _np_ptr(atom), _np_ptr(voxel),
-                                          _np_ptr(fascicle), _np_ptr(phi), ctypes.byref(self._h)))
+        if xyz is None:
+            _check("life_plan", lib.life_plan(ctypes.byref(self.dims), _np_ptr(atom), _np_ptr(voxel),
+                                              _np_ptr(fascicle), _np_ptr(phi), ctypes.byref(self._h)))
+        else:
+            _check("life_plan_ex", lib.life_plan_ex(ctypes.byref(self.dims), _np_ptr(atom), _np_ptr(voxel),
+                                                    _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz),
+                                                    ctypes.byref(self._h)))
         self.device = _torch().cuda.current_device()
 
     @classmethod
-    def from_connectome(cls, c) -> "Plan":
-        return cls(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi)
+    def from_connectome(cls, c, morton: bool = True) -> "Plan":
+        """Plan of a synthetic connectome; morton=True passes its voxel coordinates."""
+        xyz = getattr(c, "voxel_xyz", None) if morton else None
+        return cls(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi, xyz)
 
     @property
     def n_signal(self) -> int:

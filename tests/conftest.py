@@ -40,21 +40,38 @@ def relerr(x, ref):
     return float(d / n) if n > 0 else float(d)
 
 
-def reference_plan(c):
+def morton_positions(xyz):
+    """Processing position of each voxel in Morton (Z-order) sequence of its (x, y, z)
+    grid coordinates, ties by index: the key interleaves bit b of x, y, z into bits
+    3b, 3b+1, 3b+2."""
+    xyz = np.asarray(xyz, np.int64)
+    key = np.zeros(len(xyz), np.int64)
+    for b in range(16):
+        for axis in range(3):
+            key |= ((xyz[:, axis] >> b) & 1) << (3 * b + axis)
+    order = np.argsort(key, kind="stable")
+    pos = np.empty(len(xyz), np.int64)
+    pos[order] = np.arange(len(xyz))
+    return pos
+
+
+def reference_plan(c, xyz=None):
     """The restructuring plan computed independently with numpy.lexsort.
 
-    DSC order (voxel, atom, fascicle, input position); fascicle ranks by mean voxel
-    index (empty fascicles last, ties by index); WC order (rank, voxel, atom,
-    input position) given as DSC positions; segment offsets of both."""
+    DSC order (voxel, atom, fascicle, input position); voxel processing positions
+    pp (identity, or Morton order of xyz); fascicle ranks by mean pp of their
+    voxels (empty fascicles last, ties by index); WC order (rank, pp, atom, input
+    position) given as DSC positions; segment offsets of both."""
     pos = np.arange(c.nnz)
+    pp = np.arange(c.n_voxels) if xyz is None else morton_positions(xyz)
     dsc = np.lexsort((pos, c.fascicle, c.atom, c.voxel))
     cnt = np.bincount(c.fascicle, minlength=c.n_fascicles)
-    tot = np.bincount(c.fascicle, weights=c.voxel.astype(np.float64), minlength=c.n_fascicles)
+    tot = np.bincount(c.fascicle, weights=pp[c.voxel].astype(np.float64), minlength=c.n_fascicles)
     key = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.inf)
     order = np.argsort(key, kind="stable")
     rank = np.empty(c.n_fascicles, np.int64)
     rank[order] = np.arange(c.n_fascicles)
-    wc_in = np.lexsort((pos, c.atom, c.voxel, rank[c.fascicle]))
+    wc_in = np.lexsort((pos, c.atom, pp[c.voxel], rank[c.fascicle]))
     inv = np.empty(c.nnz, np.int64)
     inv[dsc] = pos
     return {

@@ -1,0 +1,113 @@
+"""GPU parity at the full synthetic scale (N_theta = 96, N_a = 1057, ~300k voxels,
+1.5M fascicles, ~90M nonzeros), with the plan the benchmark times (Morton voxel
+order).  The FP64 oracle cannot run whole operators at this size in test time,
+so outputs are checked on samples it computes one by one: a DSC row y_v needs
+only the nonzeros of voxel v, a WC entry g_f only those of fascicle f.  The
+SBB-NNLS step is checked by a property that holds at any size: every fascicle
+moves along its own projected gradient with one common step length, clipped at
+zero (eqs. 5-8), with the gradient recomputed by the oracle for a sample.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import connectome, relerr
+
+torch = pytest.importorskip("torch")
+from paper_1905_06234_amd import life  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+N_SAMPLE = 256
+
+
+@pytest.fixture(scope="module")
+def full():
+    life.load()
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    print("[full] generating the full synthetic connectome", flush=True)
+    c = connectome("full")
+    print(f"[full] nnz={c.nnz}; building the plan", flush=True)
+    plan = life.Plan.from_connectome(c)
+    yield c, plan, dev
+    plan.close()
+
+
+def _sub(c, mask):
+    return oracle.Operator(c.atom[mask], c.voxel[mask], c.fascicle[mask], c.phi[mask], c.D,
+                           c.n_voxels, c.n_fascicles)
+
+
+def _sample(rng, n, extra):
+    s = np.unique(np.concatenate([rng.choice(n, size=min(n, N_SAMPLE), replace=False), np.asarray(extra, dtype=np.int64)]))
+    return s[(s >= 0) & (s < n)]
+
+
+def test_full_dsc_sampled(full):
+    c, plan, dev = full
+    rng = np.random.default_rng(11)
+    occ = np.bincount(c.voxel, minlength=c.n_voxels)
+    vs = _sample(rng, c.n_voxels, [0, c.n_voxels - 1, int(np.argmax(occ)), int(np.argmin(occ))])
+    w = rng.random(c.n_fascicles).astype(np.float32)
+    y = plan.dsc(torch.from_numpy(c.D.ravel()).to(dev), torch.from_numpy(w).to(dev))
+    torch.cuda.synchronize()
+    y = y.cpu().double().numpy().reshape(c.n_voxels, c.n_theta)
+    ref = _sub(c, np.isin(c.voxel, vs)).dsc(w).reshape(c.n_voxels, c.n_theta)
+    assert relerr(y[vs], ref[vs]) <= TOL
+    for v in vs[:32]:                                     # per voxel as well
+        assert relerr(y[v], ref[v]) <= TOL or np.abs(ref[v]).max() == 0.0, v
+
+
+def test_full_wc_sampled(full):
+    c, plan, dev = full
+    rng = np.random.default_rng(12)
+    cnt = np.bincount(c.fascicle, minlength=c.n_fascicles)
+    fs = _sample(rng, c.n_fascicles, [0, c.n_fascicles - 1, int(np.argmax(cnt)), int(np.argmin(cnt))])
+    y = rng.standard_normal(c.n_theta * c.n_voxels, dtype=np.float32)
+    g = plan.wc(torch.from_numpy(c.D.ravel()).to(dev), torch.from_numpy(y).to(dev))
+    torch.cuda.synchronize()
+    g = g.cpu().double().numpy()
+    ref = _sub(c, np.isin(c.fascicle, fs)).wc(y)
+    assert relerr(g[fs], ref[fs]) <= TOL
+    # a per-fascicle bound scaled by the fascicle's own magnitude sum (cancellation)
+    for f in fs[:16]:
+        m = c.fascicle == f
+        scale = float(np.sum(np.abs(c.phi[m].astype(np.float64)) *
+                             np.abs(c.D[c.atom[m]]).astype(np.float64).sum(axis=1) *
+                             np.abs(y.reshape(c.n_voxels, c.n_theta)[c.voxel[m]]).max(axis=1)))
+        assert abs(g[f] - ref[f]) <= TOL * max(scale, 1e-30), f
+
+
+def test_full_sbb_step_moves_along_projected_gradient(full):
+    c, plan, dev = full
+    rng = np.random.default_rng(13)
+    b = (np.abs(rng.standard_normal(c.n_theta * c.n_voxels)) * 0.1).astype(np.float32)
+    w0 = c.w0.astype(np.float32)
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    for it in (0, 1):
+        w = torch.from_numpy(w0.copy()).to(dev)
+        st = life.new_state(dev, iteration=it)
+        plan.sbbnnls_step(D, torch.from_numpy(b).to(dev), w, st)
+        s = life.read_state(st)
+        w1 = w.cpu().double().numpy()
+        assert s["iter"] == it + 1 and np.isfinite(s["alpha"]) and s["alpha"] > 0
+        assert np.all(np.isfinite(w1)) and w1.min() >= 0.0
+        # oracle gradient on a sample of fascicles: r_v = (M w0 - b)_v on the voxels they cross
+        fs = _sample(rng, c.n_fascicles, [])
+        fs = fs[np.bincount(c.fascicle, minlength=c.n_fascicles)[fs] > 0][:96]
+        vox = np.unique(c.voxel[np.isin(c.fascicle, fs)])
+        r = _sub(c, np.isin(c.voxel, vox)).dsc(w0) - b.astype(np.float64)
+        g = _sub(c, np.isin(c.fascicle, fs)).wc(r)[fs]
+        gt = oracle.projected_gradient(w0[fs].astype(np.float64), g)
+        moving = (np.abs(gt) > 0) & (w1[fs] > 0)
+        assert moving.sum() >= 8
+        a = (w0[fs][moving] - w1[fs][moving]) / gt[moving]
+        alpha = float(np.median(a))
+        expect = np.maximum(0.0, w0[fs] - alpha * gt)
+        bound = TOL * (np.abs(w0[fs]) + np.abs(alpha * gt)) + 1e-30
+        assert np.all(np.abs(w1[fs] - expect) <= bound), it
+        assert abs(alpha - s["alpha"]) <= 1e-3 * s["alpha"], (alpha, s["alpha"])
+        still = gt == 0
+        assert np.array_equal(w1[fs][still], w0[fs][still].astype(np.float64))

@@ -50,21 +50,35 @@ def _np(t):
 
 
 _problems = {}
+_xyz = {}
 
 
 def problem(name, dev):
+    """(connectome, oracle operator, device plan) of a named case.  The synthetic
+    connectomes are planned with their voxel coordinates (Morton order); "<name>@id"
+    plans them in voxel index order; "<random shape>@xyz" gives the random COO case
+    random grid coordinates (with repeats, so ties occur)."""
     if name not in _problems:
-        if name in ("tiny", "mid"):
-            c = connectome(name)
+        base, _, variant = name.partition("@")
+        xyz = None
+        if base in ("tiny", "mid"):
+            c = connectome(base)
+            xyz = None if variant == "id" else c.voxel_xyz
         else:
-            nt, na, nv, nf, nnz, dup = RANDOM_SHAPES[name]
-            c = synth.random_coo(nt, na, nv, nf, nnz, seed=zlib.crc32(name.encode()) % 1000, duplicates=dup)
+            nt, na, nv, nf, nnz, dup = RANDOM_SHAPES[base]
+            c = synth.random_coo(nt, na, nv, nf, nnz, seed=zlib.crc32(base.encode()) % 1000, duplicates=dup)
+            if variant == "xyz":
+                rng = np.random.default_rng(zlib.crc32(name.encode()))
+                xyz = rng.integers(0, 2 * round(nv ** (1 / 3)) + 2, size=(nv, 3)).astype(np.int16)
         print(f"[parity] building plan for {name}: nnz={c.nnz}", flush=True)
-        _problems[name] = (c, oracle.Operator.from_connectome(c), life.Plan.from_connectome(c))
+        plan = life.Plan(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi,
+                         voxel_xyz=xyz)
+        _problems[name] = (c, oracle.Operator.from_connectome(c), plan)
+        _xyz[name] = xyz
     return _problems[name]
 
 
-ALL = ["tiny", "mid"] + list(RANDOM_SHAPES)
+ALL = ["tiny", "mid", "tiny@id", "mid@id"] + list(RANDOM_SHAPES) + ["r33@xyz", "r96big@xyz", "sparsevox@xyz"]
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -119,11 +133,11 @@ def test_outputs_overwritten(dev):
     assert np.isfinite(_np(g)).all()
 
 
-@pytest.mark.parametrize("name", ["tiny", "r5dup", "r129"])
+@pytest.mark.parametrize("name", ["tiny", "tiny@id", "r5dup", "r129", "r33@xyz"])
 def test_device_plan_bit_exact(name, dev):
     c, op, plan = problem(name, dev)
     ex = plan.export()
-    ref = reference_plan(c)
+    ref = reference_plan(c, _xyz[name])
     dsc = ref["dsc_perm"]
     assert np.array_equal(ex["vox_ptr"], ref["vox_ptr"])
     assert np.array_equal(ex["atom_v"], c.atom[dsc])

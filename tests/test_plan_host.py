@@ -36,8 +36,9 @@ def test_status_strings():
         assert lib.life_status_str(s).decode().startswith(life.STATUS[s])
 
 
+@pytest.mark.parametrize("morton", [False, True])
 @pytest.mark.parametrize("which", ["tiny", "mid20k", "random_dup", "ragged"])
-def test_host_plan_bit_exact(which):
+def test_host_plan_bit_exact(which, morton):
     if which == "tiny":
         c = connectome("tiny")
     elif which == "mid20k":
@@ -46,10 +47,36 @@ def test_host_plan_bit_exact(which):
         c = synth.random_coo(7, 30, 101, 57, 5000, seed=4, duplicates=True)
     else:
         c = synth.random_coo(3, 5, 9000, 3, 1234, seed=5)   # many empty voxels
-    p = life.plan_host(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle)
-    ref = reference_plan(c)
+    xyz = None
+    if morton:
+        xyz = c.voxel_xyz
+        if which in ("random_dup", "ragged"):     # random coordinates with repeats (ties)
+            xyz = np.random.default_rng(9).integers(0, 30, size=(c.n_voxels, 3)).astype(np.int16)
+    p = life.plan_host(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, xyz)
+    ref = reference_plan(c, xyz)
     for k in ("dsc_perm", "vox_ptr", "fas_rank", "wc_perm", "fas_ptr"):
         assert np.array_equal(p[k], ref[k]), k
+
+
+def test_morton_positions_pinned():
+    """The Z-order on a 2x2x2 grid visits x fastest, then y, then z; coordinate 4 in
+    x (bit 2) comes after every coordinate below 4 in all axes."""
+    from conftest import morton_positions
+    cube = np.array([(x, y, z) for z in range(2) for y in range(2) for x in range(2)])
+    assert np.array_equal(morton_positions(cube), np.arange(8))
+    pts = np.array([(4, 0, 0), (3, 3, 3), (0, 0, 1), (1, 0, 0)])
+    assert np.array_equal(morton_positions(pts), [3, 2, 1, 0])
+
+
+def test_negative_coordinate_rejected():
+    c = connectome("tiny")
+    xyz = c.voxel_xyz.copy()
+    xyz[5, 1] = -1
+    with pytest.raises(life.LifeError) as e:
+        life.plan_host(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, xyz)
+    assert e.value.status == 2
+    with pytest.raises(ValueError):
+        life.plan_host(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, xyz[:-1])
 
 
 def test_host_plan_empty():
@@ -85,10 +112,12 @@ def test_bad_dims_rejected(dims):
 def test_null_arguments_rejected():
     lib = life.load()
     d = life.Dims(4, 4, 4, 4, 3)
-    assert lib.life_plan_host(ctypes.byref(d), None, None, None, None, None, None, None, None) == 1
-    assert lib.life_plan_host(None, None, None, None, None, None, None, None, None) == 1
+    assert lib.life_plan_host(ctypes.byref(d), None, None, None, None, None, None, None, None, None) == 1
+    assert lib.life_plan_host(None, None, None, None, None, None, None, None, None, None) == 1
     h = ctypes.c_void_p()
     assert lib.life_plan(ctypes.byref(d), None, None, None, None, ctypes.byref(h)) == 1
+    assert lib.life_plan_ex(ctypes.byref(d), None, None, None, None, None, ctypes.byref(h)) == 1
+    assert lib.life_plan_ex(ctypes.byref(d), None, None, None, None, None, None) == 1
     assert lib.life_dsc(None, None, None, None, None) == 1
     assert lib.life_wc(None, None, None, None, None) == 1
     assert lib.life_sbbnnls_step(None, None, None, None, None, None) == 1
