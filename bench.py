@@ -145,7 +145,7 @@ def main():
 
     n_dsc = cnt["dsc"]
     evens = sum(1 for i in range(args.warmup, args.warmup + args.steps) if i % 2 == 0)
-    n_wc = cnt["wc_sum"] + evens          # the even-only launches return at once on odd iterations
+    n_wc = cnt["wc_sum"] + evens          # the second WC runs on even iterations only (Algorithm 1)
     pairs = (n_dsc + n_wc) / 2.0
     value = d.nnz * pairs / wall
     avg = {k: (ms[k] / cnt[k] if cnt[k] else 0.0) for k in ms}

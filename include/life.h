@@ -83,8 +83,8 @@ typedef enum {
     LIFE_K_MASK = 3,       /* projected gradient g~ and ||g~||^2 partials          */
     LIFE_K_ALPHA = 4,      /* step length from the partial sums                   */
     LIFE_K_UPDATE = 5,     /* w <- [w - alpha g~]_+                               */
-    LIFE_K_WC_Z_EVEN = 6,  /* WC pass 1 of v'' = M^T v' (runs on even i only)     */
-    LIFE_K_WC_SUM_EVEN = 7,/* WC pass 2 of v'' (runs on even i only)              */
+    LIFE_K_WC_Z_2ND = 6,   /* WC pass 1 of v'' = M^T v' (SBB, gated by parity)    */
+    LIFE_K_WC_SUM_2ND = 7, /* WC pass 2 of v'' (SBB, gated by parity)             */
     LIFE_K_PERMUTE = 8,    /* weights into the plan's fascicle order              */
     LIFE_K_COUNT = 9
 } life_kernel_kind;
@@ -156,8 +156,8 @@ life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v
  * form of the inner loop): y[t + N_theta*v] = sum over nonzeros c of voxel v of
  * D[t + N_theta*atom_c] * phi_c * w[fascicle_c].
  *   D (device, N_theta*N_a), w (device, N_f) are read; y (device, N_theta*N_v) is
- *   overwritten (voxels with no nonzero get 0).  Nonzeros whose phi_c*w[f_c] is
- *   zero are skipped (the paper's use of the sparsity of w).
+ *   overwritten (voxels with no nonzero get 0).  Every nonzero is processed: a
+ *   zero weight contributes an exact zero (no data-dependent branches).
  * Errors: LIFE_EINVAL (NULL plan or pointer with a nonzero size), LIFE_EDEVICE. */
 life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream);
 
@@ -186,10 +186,25 @@ life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, 
 life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
                               life_sbb_state *state, void *stream);
 
+/* One SBB-NNLS iteration with the step lengths of eqs. 7-8 as printed, i.e. the
+ * classic lagged Barzilai-Borwein form: alpha^(i) is evaluated at q, the
+ * projected gradient of the previous iterate (at i = 0, the current one):
+ *   r, g, g~ as in life_sbbnnls_step;   v' = M q;
+ *   i even: alpha = <q,q> / <v',v'>                                 (eq. 7)
+ *   i odd : v'' = M^T v';  alpha = <v',v'> / <v'',v''>               (eq. 8)
+ *   (a zero denominator gives alpha = 0);   w <- [w - alpha g~]_+   (eq. 5).
+ *   gt_prev (device, N_f, caller's fascicle order): read as q when i > 0 (not
+ *   read at i = 0), then overwritten with this iteration's g~, ready for the
+ *   next call.  Two DSC and, on odd i, two WC per call.
+ *   Other arguments, state and errors as life_sbbnnls_step. */
+life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D, const float *b, float *w,
+                                     float *gt_prev, life_sbb_state *state, void *stream);
+
 /* Profiling hooks for the benchmark: when enabled, every kernel the plan
- * launches is bracketed by HIP events on its stream.  The two even-only WC
- * launches of life_sbbnnls_step are recorded under their own kinds: on odd
- * iterations they are enqueued but return at once.  life_profile_read
+ * launches is bracketed by HIP events on its stream.  The two launches of an
+ * SBB step's second WC (v'' = M^T v') are recorded under their own kinds: on
+ * the iterations that do not need it they are enqueued but return at once.
+ * life_profile_read
  * synchronizes those events, writes per-kind total milliseconds and launch
  * counts (arrays of LIFE_K_COUNT entries, host; either may be NULL) and
  * resets the record. */

@@ -12,6 +12,10 @@ What is computed and where it comes from (arxiv 1905.06234):
   into the Phi values.  Plain C loop over the nonzeros in input order
   (``life_oracle.c``), double precision.
 * ``wc``   - g = M^T y, the transpose product inside the gradient of eq. 6.
+* ``dd``   - d<ybar, M(D) w>/dD, the derivative of the DSC product with respect
+  to the dictionary (y is linear in D through eq. 3/4); ``loss_grads`` gives
+  both gradients of ||y_obs - M(D) w||^2.  The paper fits w only; this serves
+  dictionary learning through the same encoding.
 * ``sbb_step`` - one iteration of SBB-NNLS in the matrix form of Algorithm 1
   (Sec. 2.1), with these readings of points the text leaves open:
     - iterations are counted from i = 0; odd i uses alpha = <g~,g~>/<Mg~,Mg~>,
@@ -60,7 +64,7 @@ def _load():
     if _lib is None:
         lib = ctypes.CDLL(build())
         P = ctypes.c_void_p
-        for name in ("oracle_dsc", "oracle_wc"):
+        for name in ("oracle_dsc", "oracle_wc", "oracle_dd"):
             fn = getattr(lib, name)
             fn.restype = None
             fn.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
@@ -133,6 +137,33 @@ class Operator:
         _load().oracle_wc(self.nnz, self.n_theta, self.n_fascicles, _ptr(self.atom), _ptr(self.voxel),
                           _ptr(self.fascicle), _ptr(self._phi64), _ptr(self._D64), _ptr(y64), _ptr(g))
         return g
+
+    def dd(self, w: np.ndarray, ybar: np.ndarray) -> np.ndarray:
+        """d<ybar, M(D) w>/dD, shape (n_atoms, n_theta) like D."""
+        w64 = np.ascontiguousarray(w, dtype=np.float64)
+        y64 = np.ascontiguousarray(ybar, dtype=np.float64)
+        if w64.shape != (self.n_fascicles,) or y64.shape != (self.n_theta * self.n_voxels,):
+            raise ValueError("w or ybar has the wrong length")
+        na = int(self._D64.shape[0])
+        dD = np.empty((na, self.n_theta), dtype=np.float64)
+        _load().oracle_dd(self.nnz, self.n_theta, na, _ptr(self.atom), _ptr(self.voxel), _ptr(self.fascicle),
+                          _ptr(self._phi64), _ptr(w64), _ptr(y64), _ptr(dD))
+        return dD
+
+    def with_dictionary(self, D: np.ndarray) -> "Operator":
+        """The same nonzeros with another dictionary."""
+        return Operator(self.atom, self.voxel, self.fascicle, self._phi64, D, self.n_voxels, self.n_fascicles)
+
+    def loss(self, w: np.ndarray, y_obs: np.ndarray) -> float:
+        """L = ||y_obs - M w||^2 (no 1/2), the dictionary-fitting loss."""
+        r = self.dsc(w) - np.asarray(y_obs, dtype=np.float64)
+        return float(r @ r)
+
+    def loss_grads(self, w: np.ndarray, y_obs: np.ndarray):
+        """(dL/dD, dL/dw) of L = ||y_obs - M(D) w||^2: with r = M w - y_obs,
+        dL/dw = 2 M^T r and dL/dD = 2 dd(w, r)."""
+        r = self.dsc(w) - np.asarray(y_obs, dtype=np.float64)
+        return 2.0 * self.dd(w, r), 2.0 * self.wc(r)
 
     def objective(self, w: np.ndarray, b: np.ndarray) -> float:
         """f(w) = 1/2 ||M w - b||^2  (eq. 2)."""

@@ -57,3 +57,24 @@ void oracle_wc(int64_t nnz, int32_t n_theta, int32_t n_fascicles,
         g[fascicle[c]] += phi[c] * dot;
     }
 }
+
+/* Gradient of <ybar, M(D) w> with respect to the dictionary.  y = M(D) w is
+ * linear in D (eq. 3/4: each nonzero adds D[:, atom_c] * phi_c * w[f_c] to
+ * voxel_c's signal), so
+ *   dD[t + Nt*a] = sum over nonzeros c with atom_c = a of
+ *                  phi_c * w[fascicle_c] * ybar[t + Nt*voxel_c].
+ * (The paper fits w only; this is the derivative a learned dictionary needs.)
+ * dD (Nt*Na) is overwritten. */
+void oracle_dd(int64_t nnz, int32_t n_theta, int32_t n_atoms,
+               const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
+               const double *phi, const double *w, const double *ybar, double *dD)
+{
+    memset(dD, 0, sizeof(double) * (size_t)n_theta * (size_t)n_atoms);
+    for (int64_t c = 0; c < nnz; ++c) {
+        const double s = phi[c] * w[fascicle[c]];
+        const double *yv = ybar + (int64_t)n_theta * voxel[c];
+        double *d = dD + (int64_t)n_theta * atom[c];
+        for (int32_t t = 0; t < n_theta; ++t)
+            d[t] += s * yv[t];
+    }
+}

@@ -40,6 +40,15 @@ using life::kWaveVoxels;
 
 namespace {
 
+// Launch gate of the products that only some SBB iterations need: with st set,
+// the kernel runs only when the iteration count's parity equals par, decided on
+// the device so a whole iteration is enqueued without a host round trip.
+struct Gate {
+    const life_sbb_state *st;
+    int par;
+};
+__device__ inline bool gated_off(const Gate &g) { return g.st && (int)(g.st->iter & 1) != g.par; }
+
 constexpr int kBlock = 256;                  // threads per block of the generic / glue kernels
 constexpr int kSeg = 32;                     // lanes per voxel segment (generic kernels)
 constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block (generic kernels)
@@ -325,9 +334,9 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
                                                    const float *__restrict__ D,
                                                    const float *__restrict__ y,
                                                    float *__restrict__ z, int nth, int na, int T, int TA,
-                                                   bool vec, const life_sbb_state *__restrict__ gate)
+                                                   bool vec, Gate gate)
 {
-    if (gate && (gate->iter & 1)) return;   // even-iteration launch: uniform exit on odd i
+    if (gated_off(gate)) return;   // uniform over the grid
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
@@ -484,10 +493,9 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
                                                   const float *__restrict__ phi,
                                                   const float *__restrict__ D,
                                                   const float *__restrict__ y,
-                                                  float *__restrict__ z, int nth, int nv,
-                                                  const life_sbb_state *__restrict__ gate)
+                                                  float *__restrict__ z, int nth, int nv, Gate gate)
 {
-    if (gate && (gate->iter & 1)) return;
+    if (gated_off(gate)) return;
     const int lane = threadIdx.x & (kSeg - 1);
     const int v = blockIdx.x * kSegPerBlock + (threadIdx.x / kSeg);
     if (v >= nv) return;
@@ -531,9 +539,9 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
                                                     const float *__restrict__ z,
                                                     const int32_t *__restrict__ gmap,
                                                     float *__restrict__ g, double *__restrict__ part,
-                                                    int nf, const life_sbb_state *__restrict__ gate)
+                                                    int nf, Gate gate)
 {
-    if (gate && (gate->iter & 1)) return;   // uniform over the grid
+    if (gated_off(gate)) return;   // uniform over the grid
     const int lane = threadIdx.x & (kFasLanes - 1);
     const int f = blockIdx.x * kFasPerBlock + threadIdx.x / kFasLanes;
     float s = 0.f;
@@ -579,22 +587,32 @@ __global__ __launch_bounds__(kBlock) void k_mask(const float *__restrict__ w, co
     block_sum_store<kBlock>(sq, part);
 }
 
-// alpha from the partial sums (Algorithm 1 (a)/(b)); records the state; i += 1.
+// alpha from the partial sums; records the state; i += 1.
+//   Algorithm 1 (lagged = 0): odd i  alpha = <g~,g~> / <Mg~,Mg~>
+//                             even i alpha = <Mg~,Mg~> / <M^T M g~, M^T M g~>
+//   eqs. 7-8 (lagged = 1), q = g~ of the previous iterate (the current one at i = 0):
+//                             even i alpha = <q,q> / <Mq,Mq>
+//                             odd i  alpha = <Mq,Mq> / <M^T M q, M^T M q>
+// p_vp / p_vpp hold the partial squared norms of M q and M^T M q (q = g~ in
+// Algorithm 1); p_q those of q (NULL: q = g~).
 __global__ __launch_bounds__(kAlphaThreads) void k_alpha(const double *__restrict__ p_r, int n_r,
                                                           const double *__restrict__ p_gt, int n_gt,
+                                                          const double *__restrict__ p_q, int n_q,
                                                           const double *__restrict__ p_vp, int n_vp,
                                                           const double *__restrict__ p_vpp, int n_vpp,
-                                                          life_sbb_state *__restrict__ st)
+                                                          life_sbb_state *__restrict__ st, int lagged)
 {
     const int64_t it = st->iter;
     const bool odd = (it & 1) != 0;
+    const bool first_form = lagged ? !odd : odd;      // <q,q> / <Mq,Mq>
     const double r2 = block_sum_array(p_r, n_r);
     const double gt2 = block_sum_array(p_gt, n_gt);
+    const double q2 = p_q ? block_sum_array(p_q, n_q) : gt2;
     const double vp2 = block_sum_array(p_vp, n_vp);
-    const double vpp2 = odd ? 0.0 : block_sum_array(p_vpp, n_vpp);
+    const double vpp2 = first_form ? 0.0 : block_sum_array(p_vpp, n_vpp);
     if (threadIdx.x == 0) {
-        const double num = odd ? gt2 : vp2;
-        const double den = odd ? vp2 : vpp2;
+        const double num = first_form ? q2 : vp2;
+        const double den = first_form ? vp2 : vpp2;
         st->alpha = den > 0.0 ? num / den : 0.0;
         st->obj = 0.5 * r2;
         st->gt_norm2 = gt2;
@@ -604,16 +622,36 @@ __global__ __launch_bounds__(kAlphaThreads) void k_alpha(const double *__restric
     }
 }
 
+// q for the lagged step: q[r] = g~ of the previous iterate (caller order, in
+// gt_prev) or, at i = 0, the current g~; partial ||q||^2.
+__global__ __launch_bounds__(kBlock) void k_lag_q(const float *__restrict__ gt_prev, const int32_t *__restrict__ ext,
+                                                   const float *__restrict__ gt, float *__restrict__ q,
+                                                   double *__restrict__ part, const life_sbb_state *__restrict__ st,
+                                                   int nf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool first = st->iter == 0;
+    double sq = 0.0;
+    if (i < nf) {
+        const float v = first ? gt[i] : gt_prev[ext[i]];
+        q[i] = v;
+        sq = (double)v * (double)v;
+    }
+    block_sum_store<kBlock>(sq, part);
+}
+
 // w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.  The
 // iterate and g~ are in fascicle-rank order; w_out is in the caller's order.
 __global__ __launch_bounds__(kBlock) void k_update(float *__restrict__ w_out, const float *__restrict__ w_rank,
                                                     const float *__restrict__ gt, const int32_t *__restrict__ ext,
-                                                    const life_sbb_state *__restrict__ st, int nf)
+                                                    const life_sbb_state *__restrict__ st, float *__restrict__ gt_out,
+                                                    int nf)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nf) return;
     const double x = (double)w_rank[i] - st->alpha * (double)gt[i];
     w_out[ext[i]] = x > 0.0 ? (float)x : 0.0f;
+    if (gt_out) gt_out[ext[i]] = gt[i];
 }
 
 // w_rank[r] = w[ext[r]]: weights into fascicle-rank order.
@@ -660,8 +698,8 @@ struct life_plan_s {
     float *w_rank = nullptr;      // [Nf] weights in rank order
     float *z = nullptr;           // [nnz]
     float *r = nullptr, *vp = nullptr;                  // [Nt*Nv]
-    float *g = nullptr, *gt = nullptr, *vpp = nullptr;  // [Nf]
-    double *part = nullptr;       // 4 regions of part_stride
+    float *g = nullptr, *gt = nullptr, *vpp = nullptr, *q = nullptr;  // [Nf]
+    double *part = nullptr;       // 5 regions of part_stride
     int64_t part_stride = 0;
     // profiling
     bool profile = false;
@@ -697,7 +735,7 @@ void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->wave_work, p->atom_c, p->fas_c,
                     p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
-                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->part};
+                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -808,12 +846,12 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
 }
 
 life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, const int32_t *gmap,
-                       double *part, const life_sbb_state *gate, hipStream_t s)
+                       double *part, Gate gate, hipStream_t s)
 {
     const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
     life_status st = LIFE_OK;
     if (nv > 0 && p->dims.nnz > 0) {
-        const int kind = gate ? LIFE_K_WC_Z_EVEN : LIFE_K_WC_Z;
+        const int kind = gate.st ? LIFE_K_WC_Z_2ND : LIFE_K_WC_Z;
         if (chunked(p)) {
             const int nc = p->tile.row_floats / 32;
             const size_t lds = tile_lds_bytes(p);
@@ -835,7 +873,7 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
     }
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
-        st = launch(p, gate ? LIFE_K_WC_SUM_EVEN : LIFE_K_WC_SUM, s, [&] {
+        st = launch(p, gate.st ? LIFE_K_WC_SUM_2ND : LIFE_K_WC_SUM, s, [&] {
             k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_z : p->wc_perm, p->z, gmap, g,
                                              part, nf, gate);
         });
@@ -957,7 +995,8 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     chk(dalloc(&p->g, d.n_fascicles));
     chk(dalloc(&p->gt, d.n_fascicles));
     chk(dalloc(&p->vpp, d.n_fascicles));
-    chk(dalloc(&p->part, 4 * nb));
+    chk(dalloc(&p->q, d.n_fascicles));
+    chk(dalloc(&p->part, 5 * nb));
     if (e == hipSuccess && n_chunks > 0) e = allow_lds();
     if (e != hipSuccess) {
         free_plan(p);
@@ -1053,8 +1092,68 @@ extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y,
         return LIFE_EINVAL;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_wc(plan, D, y, g, plan->fas_ext, nullptr, nullptr, static_cast<hipStream_t>(stream));
+    return enqueue_wc(plan, D, y, g, plan->fas_ext, nullptr, Gate{nullptr, 0}, static_cast<hipStream_t>(stream));
 }
+
+namespace {
+
+// One SBB-NNLS iteration; gt_prev != NULL selects the lagged (eqs. 7-8) step.
+life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float *w, float *gt_prev,
+                        life_sbb_state *state, hipStream_t s)
+{
+    const life_dims &d = plan->dims;
+    const bool lagged = gt_prev != nullptr;
+    const int64_t ps = plan->part_stride;
+    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps, *p_vpp = plan->part + 3 * ps;
+    double *p_q = plan->part + 4 * ps;
+    const int nv = d.n_voxels, nf = d.n_fascicles;
+    const int nb_dsc = nv > 0 ? dsc_partials(plan) : 0;
+    const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
+    const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
+    life_status st;
+    // weights into fascicle-rank order (every vector of the step below stays in it)
+    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
+    // r = M w - b, partial ||r||^2
+    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
+    // g = M^T r
+    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
+    // g~ and ||g~||^2
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_MASK, s, [&] {
+            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
+        });
+        if (st != LIFE_OK) return st;
+    }
+    // q: g~ (Algorithm 1) or the previous iterate's g~ (eqs. 7-8), and ||q||^2
+    const float *q = plan->gt;
+    if (lagged && nf > 0) {
+        st = launch(plan, LIFE_K_MASK, s, [&] {
+            k_lag_q<<<nb_mask, kBlock, 0, s>>>(gt_prev, plan->fas_ext, plan->gt, plan->q, p_q, state, nf);
+        });
+        if (st != LIFE_OK) return st;
+        q = plan->q;
+    }
+    // v' = M q, ||v'||^2
+    if ((st = enqueue_dsc(plan, D, q, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
+    // v'' = M^T v', ||v''||^2, on the iterations of the second alpha form (even i
+    // in Algorithm 1, odd i in eqs. 7-8); the kernels test the parity on the device
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, Gate{state, lagged ? 1 : 0}, s)) != LIFE_OK)
+        return st;
+    st = launch(plan, LIFE_K_ALPHA, s, [&] {
+        k_alpha<<<1, kAlphaThreads, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, lagged ? p_q : nullptr, nb_mask, p_vp, nb_dsc,
+                                            p_vpp, nb_sum, state, lagged ? 1 : 0);
+    });
+    if (st != LIFE_OK) return st;
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_UPDATE, s, [&] {
+            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, state,
+                                                         lagged ? gt_prev : nullptr, nf);
+        });
+    }
+    return st;
+}
+
+}  // namespace
 
 extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
                                          life_sbb_state *state, void *stream)
@@ -1066,41 +1165,20 @@ extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const
         return LIFE_EINVAL;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t ps = plan->part_stride;
-    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps, *p_vpp = plan->part + 3 * ps;
-    const int nv = d.n_voxels, nf = d.n_fascicles;
-    const int nb_dsc = nv > 0 ? dsc_partials(plan) : 0;
-    const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
-    const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
-    life_status st;
-    // weights into fascicle-rank order (every vector of the step below stays in it)
-    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
-    // r = M w - b, partial ||r||^2
-    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
-    // g = M^T r
-    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, nullptr, s)) != LIFE_OK) return st;
-    // g~ and ||g~||^2
-    if (nf > 0) {
-        st = launch(plan, LIFE_K_MASK, s, [&] {
-            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
-        });
-        if (st != LIFE_OK) return st;
-    }
-    // v' = M g~, ||v'||^2
-    if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
-    // even iterations: v'' = M^T v', ||v''||^2 (the kernels test the parity on the device)
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, state, s)) != LIFE_OK) return st;
-    st = launch(plan, LIFE_K_ALPHA, s, [&] {
-        k_alpha<<<1, kAlphaThreads, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, p_vp, nb_dsc, p_vpp, nb_sum, state);
-    });
-    if (st != LIFE_OK) return st;
-    if (nf > 0) {
-        st = launch(plan, LIFE_K_UPDATE, s, [&] {
-            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, state, nf);
-        });
-    }
-    return st;
+    return enqueue_sbb(plan, D, b, w, nullptr, state, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D, const float *b, float *w,
+                                                float *gt_prev, life_sbb_state *state, void *stream)
+{
+    if (!plan || !state) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(b, (int64_t)d.n_theta * d.n_voxels) ||
+        !need(w, d.n_fascicles) || !need(gt_prev, d.n_fascicles))
+        return LIFE_EINVAL;
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    return enqueue_sbb(plan, D, b, w, gt_prev, state, static_cast<hipStream_t>(stream));
 }
 
 extern "C" life_status life_profile_enable(life_plan_t plan, int enable)

@@ -19,7 +19,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblife.so")
 
-KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_even", "wc_sum_even", "permute")
+KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_2nd", "wc_sum_2nd", "permute")
 STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
 STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
 
@@ -53,6 +53,7 @@ _SIGS = {
     "life_dsc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_wc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_sbbnnls_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "life_sbbnnls_step_lagged": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "life_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "life_profile_read": (ctypes.c_int, [_P, _P, _P]),
 }
@@ -222,16 +223,31 @@ class Plan:
                                          _dev_f32(g, self.dims.n_fascicles, "g"), _stream(stream, y.device)))
         return g
 
-    def sbbnnls_step(self, D, b, w, state, stream=None):
-        """One SBB-NNLS iteration in place on w; state from new_state()."""
+    @staticmethod
+    def _state(state):
         torch = _torch()
         if not (isinstance(state, torch.Tensor) and state.is_cuda and state.numel() * state.element_size() == 48
                 and state.is_contiguous()):
             raise ValueError("state must be a 48-byte contiguous device tensor (see new_state)")
+        return ctypes.c_void_p(state.data_ptr())
+
+    def sbbnnls_step(self, D, b, w, state, stream=None):
+        """One SBB-NNLS iteration (Algorithm 1) in place on w; state from new_state()."""
+        st = self._state(state)
         _check("life_sbbnnls_step",
                load().life_sbbnnls_step(self._h, self._d(D), _dev_f32(b, self.n_signal, "b"),
-                                        _dev_f32(w, self.dims.n_fascicles, "w"), ctypes.c_void_p(state.data_ptr()),
-                                        _stream(stream, w.device)))
+                                        _dev_f32(w, self.dims.n_fascicles, "w"), st, _stream(stream, w.device)))
+        return w
+
+    def sbbnnls_step_lagged(self, D, b, w, gt_prev, state, stream=None):
+        """One lagged-BB SBB-NNLS iteration (eqs. 7-8) in place on w; gt_prev (N_f
+        floats on the device) carries the projected gradient from call to call."""
+        st = self._state(state)
+        nf = self.dims.n_fascicles
+        _check("life_sbbnnls_step_lagged",
+               load().life_sbbnnls_step_lagged(self._h, self._d(D), _dev_f32(b, self.n_signal, "b"),
+                                               _dev_f32(w, nf, "w"), _dev_f32(gt_prev, nf, "gt_prev"), st,
+                                               _stream(stream, w.device)))
         return w
 
     def export(self) -> Dict[str, np.ndarray]:

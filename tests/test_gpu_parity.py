@@ -184,6 +184,53 @@ def test_sbb_step_teacher_forced(name, iters, dev):
         w = ref.w.astype(np.float32)
 
 
+@pytest.mark.parametrize("name,iters", [("tiny", (0, 1, 2, 3, 8, 9)), ("mid", (0, 1, 2)), ("r100", (0, 1, 4, 5)),
+                                        ("r33@xyz", (0, 1, 2))])
+def test_sbb_lagged_step_teacher_forced(name, iters, dev):
+    c, op, plan = problem(name, dev)
+    b32 = _signal(name.partition("@")[0], op, c)
+    D, b = _t(c.D, dev), _t(b32, dev)
+    w = c.w0.astype(np.float32)
+    gprev = None
+    for i in range(max(iters) + 1):
+        ref = oracle.sbb_step_lagged(op, w, i, b32, gprev)
+        if i in iters:
+            wt = _t(w, dev)
+            # at i = 0 the previous gradient must not be read: poison it
+            gp = torch.full((c.n_fascicles,), float("nan"), device=dev) if gprev is None else _t(gprev, dev)
+            st = life.new_state(dev, iteration=i)
+            plan.sbbnnls_step_lagged(D, b, wt, gp, st)
+            s = life.read_state(st)
+            assert s["iter"] == i + 1
+            assert relerr(_np(wt), ref.w) <= TOL, (name, i)
+            assert abs(s["alpha"] - ref.alpha) <= TOL * ref.alpha, (name, i)
+            assert abs(s["obj"] - ref.f) <= TOL * ref.f, (name, i)
+            assert abs(s["num"] - ref.num) <= TOL * ref.num and abs(s["den"] - ref.den) <= TOL * ref.den
+            assert relerr(_np(gp), ref.gt) <= TOL, (name, i)       # g~ handed to the next call
+        w = ref.w.astype(np.float32)
+        gprev = ref.gt.astype(np.float32)
+
+
+def test_sbb_lagged_free_running_tiny(dev):
+    c, op, plan = problem("tiny", dev)
+    b32 = _signal("tiny", op, c)
+    D, b = _t(c.D, dev), _t(b32, dev)
+    w = _t(c.w0, dev)
+    gp = torch.zeros(c.n_fascicles, device=dev)
+    st = life.new_state(dev)
+    f_gpu = []
+    for _ in range(20):
+        plan.sbbnnls_step_lagged(D, b, w, gp, st)
+        f_gpu.append(life.read_state(st)["obj"])
+    wr, gprev, f_ref = c.w0.astype(np.float64), None, []
+    for i in range(20):
+        r = oracle.sbb_step_lagged(op, wr, i, b32, gprev)
+        f_ref.append(r.f)
+        wr, gprev = r.w, r.gt
+    assert np.max(np.abs(np.array(f_gpu) - np.array(f_ref)) / np.array(f_ref)) <= 1e-4
+    assert f_gpu[-1] < 0.5 * f_gpu[0]
+
+
 def test_sbb_free_running_tiny(dev):
     c, op, plan = problem("tiny", dev)
     b32 = _signal("tiny", op, c)

@@ -37,8 +37,8 @@ def _golden():
         if not line or line.startswith("#"):
             continue
         tok = line.split()
-        if tok[0] == "sbb":
-            sbb.append(tok[1:])
+        if tok[0] in ("sbb", "lag"):
+            sbb.append(tok)
         else:
             kv[tok[0]] = tok[1:]
     return kv, sbb
@@ -77,6 +77,7 @@ def test_hand_example_products():
 def test_hand_example_sbb_steps():
     _, cases = _golden()
     _, op = _hand_operator()
+    cases = [c[1:] for c in cases if c[0] == "sbb"]
     assert len(cases) == 6
     for case in cases:
         name, i = case[0], int(case[1])
@@ -89,6 +90,30 @@ def test_hand_example_sbb_steps():
         assert s.alpha == pytest.approx(alpha, rel=1e-14, abs=1e-15), name
         np.testing.assert_allclose(s.w, w_next, rtol=1e-14, atol=1e-15, err_msg=name)
         assert np.all(np.signbit(s.w) == False)  # noqa: E712  (+0.0 after projection)
+
+
+def test_hand_example_lagged_steps():
+    _, cases = _golden()
+    _, op = _hand_operator()
+    cases = [c[1:] for c in cases if c[0] == "lag"]
+    assert len(cases) == 5
+    for case in cases:
+        name, i = case[0], int(case[1])
+        w = np.array([float(Fraction(x)) for x in case[2:4]])
+        b = np.array([float(Fraction(x)) for x in case[4:8]])
+        q = None if case[8] == "-" else np.array([float(Fraction(x)) for x in case[8:10]])
+        f, alpha = float(Fraction(case[10])), float(Fraction(case[11]))
+        w_next = np.array([float(Fraction(x)) for x in case[12:14]])
+        s = oracle.sbb_step_lagged(op, w, i, b, q)
+        assert s.f == pytest.approx(f, rel=1e-14), name
+        assert s.alpha == pytest.approx(alpha, rel=1e-14), (name, i)
+        np.testing.assert_allclose(s.w, w_next, rtol=1e-14, atol=1e-15, err_msg=f"{name} {i}")
+
+
+def test_hand_example_dictionary_gradient():
+    kv, op = _hand_operator()
+    dD = op.dd(np.array(kv["dd_w"], dtype=np.float64), np.array(kv["dd_ybar"], dtype=np.float64))
+    assert np.array_equal(dD.ravel(), np.array(kv["dd_D"], dtype=np.float64))
 
 
 # ----------------------------------------------------------------------------- brute force
@@ -347,6 +372,7 @@ def test_pins_catch_planted_step_mistakes(name):
     step = _mutant_steps()[name]
     kv, op_h = _hand_operator()
     _, cases = _golden()
+    cases = [c[1:] for c in cases if c[0] == "sbb"]
     caught = False
     for case in cases:                       # hand-worked cases
         i = int(case[1])
@@ -377,3 +403,74 @@ def test_pins_catch_transposed_dictionary():
     bad = np.ascontiguousarray(c.D.T.reshape(c.D.shape))
     op_bad = oracle.Operator(c.atom, c.voxel, c.fascicle, c.phi, bad, c.n_voxels, c.n_fascicles)
     assert relerr(op_bad.dsc(c.w0), M @ c.w0.astype(np.float64)) > 1e-3
+
+
+# ----------------------------------------------------------------------------- dictionary gradient
+
+
+def _dd_cases():
+    yield "tiny", connectome("tiny")
+    yield "random_dup", synth.random_coo(7, 30, 101, 57, 5000, seed=4, duplicates=True)
+
+
+@pytest.mark.parametrize("which", ["tiny", "random_dup"])
+def test_dd_adjoint_of_dsc_in_the_dictionary(which):
+    """y = M(D) w is linear in D, so <dd(w, ybar), E> = <ybar, M(E) w> for any E."""
+    c = dict(_dd_cases())[which]
+    op = oracle.Operator.from_connectome(c)
+    rng = np.random.default_rng(21)
+    w = rng.random(c.n_fascicles)
+    ybar = rng.standard_normal(c.n_theta * c.n_voxels)
+    dD = op.dd(w, ybar)
+    for _ in range(3):
+        E = rng.standard_normal(c.D.shape)
+        lhs = float(np.sum(dD * E))
+        rhs = float(ybar @ op.with_dictionary(E).dsc(w))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(rhs) + float(np.sum(np.abs(dD) * np.abs(E)))), which
+
+
+def test_loss_gradients_match_central_differences():
+    """L = ||y_obs - M(D) w||^2 is quadratic in D and in w: central differences
+    are exact up to rounding (FP64, h = 1e-6, rel <= 1e-6)."""
+    c = connectome("tiny")
+    op = oracle.Operator.from_connectome(c)
+    rng = np.random.default_rng(22)
+    w = c.w0.astype(np.float64)
+    y_obs = rng.standard_normal(c.n_theta * c.n_voxels)
+    gD, gw = op.loss_grads(w, y_obs)
+    h = 1e-6
+    for _ in range(4):
+        E = rng.standard_normal(c.D.shape)
+        fd = (op.with_dictionary(c.D + h * E).loss(w, y_obs) - op.with_dictionary(c.D - h * E).loss(w, y_obs)) / (2 * h)
+        assert abs(fd - float(np.sum(gD * E))) <= 1e-6 * abs(fd)
+        e = rng.standard_normal(c.n_fascicles)
+        fd = (op.loss(w + h * e, y_obs) - op.loss(w - h * e, y_obs)) / (2 * h)
+        assert abs(fd - float(gw @ e)) <= 1e-6 * abs(fd)
+
+
+def test_dd_pin_catches_planted_mistakes():
+    """Plausible slips in the dictionary gradient (a dropped phi, w read by voxel,
+    ybar read at the atom's column) all fail the adjoint identity."""
+    c = connectome("tiny")
+    op = oracle.Operator.from_connectome(c)
+    rng = np.random.default_rng(23)
+    w = rng.random(c.n_fascicles)
+    ybar = rng.standard_normal(c.n_theta * c.n_voxels)
+    Y = ybar.reshape(c.n_voxels, c.n_theta)
+    phi = c.phi.astype(np.float64)
+
+    def scatter(scale, cols):
+        out = np.zeros_like(c.D, dtype=np.float64)
+        np.add.at(out, c.atom, scale[:, None] * cols)
+        return out
+
+    mutants = {
+        "no_phi": scatter(w[c.fascicle], Y[c.voxel]),
+        "w_by_voxel": scatter(phi * w[c.voxel % c.n_fascicles], Y[c.voxel]),
+        "ybar_at_atom": scatter(phi * w[c.fascicle], Y[c.atom % c.n_voxels]),
+    }
+    E = rng.standard_normal(c.D.shape)
+    rhs = float(ybar @ op.with_dictionary(E).dsc(w))
+    assert abs(float(np.sum(op.dd(w, ybar) * E)) - rhs) <= 1e-10 * abs(rhs)
+    for name, dD in mutants.items():
+        assert abs(float(np.sum(dD * E)) - rhs) > 1e-6 * abs(rhs), name
