@@ -17,8 +17,12 @@ random sample of the same nonzeros.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,8 +33,131 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector; a plain v_fma_f32 loop reached 132 TFLOP/s here
 
 
+# rocprofv3 commands whose outputs --summarize reads (run from /tmp with
+# TMPDIR=/tmp; the synthetic connectome cached through LIFE_SYNTH_CACHE)
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof/trace -o run -- "
+             "python3 $R/bench.py --steps 6 --warmup 2 --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/fetch -o run -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/write -o run -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "tcc": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d $R/gpurun_out/prof/tcc -o run -- "
+           "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "copyf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/copyf -o run -- "
+             "python3 $R/bench.py --copy-probe",
+    "copyw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/copyw -o run -- "
+             "python3 $R/bench.py --copy-probe",
+}
+KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_chunk", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """SHA-256 of the library sources: counters recorded for other sources are stale."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1905_06234_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "life.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    m = re.search(r"(k_[a-z_0-9]+(<\d+>)?|__amd_rocclr_\w+)", name)
+    return m.group(1) if m else name[:40]
+
+
+def _counter_means(d: str):
+    """{kernel: (dispatches, mean value)} over the counter rows of a rocprofv3 csv run."""
+    acc = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            k = (_short(r["Kernel_Name"]), r["Counter_Name"])
+            n, t = acc.get(k, (0, 0.0))
+            acc[k] = (n + 1, t + float(r["Counter_Value"]))
+    return {k: (n, t / n) for k, (n, t) in acc.items()}
+
+
+def summarize(prof_dir: str, workload: str):
+    """Turn the rocprofv3 outputs of PROFILE_COMMANDS into profiles/<workload>_*.{md,json}."""
+    stats = {}
+    for path in glob.glob(os.path.join(prof_dir, "trace", "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            stats[_short(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]))
+    fetch, write = _counter_means(os.path.join(prof_dir, "fetch")), _counter_means(os.path.join(prof_dir, "write"))
+    tcc = _counter_means(os.path.join(prof_dir, "tcc"))
+    cf, cw = _counter_means(os.path.join(prof_dir, "copyf")), _counter_means(os.path.join(prof_dir, "copyw"))
+    copy_bytes = 256 << 20
+
+    def copy_kib(m, counter):
+        vals = [v for (k, c), (n, v) in m.items() if c == counter and "copyBuffer" in k]
+        return max(vals) if vals else None
+    ckf, ckw = copy_kib(cf, "FETCH_SIZE"), copy_kib(cw, "WRITE_SIZE")
+    ff = copy_bytes / (ckf * 1024) if ckf else None
+    fw = copy_bytes / (ckw * 1024) if ckw else None
+    kernels = {}
+    for name in sorted({k for (k, c) in fetch} | set(stats)):
+        if not name.startswith("k_"):
+            continue
+        e = {"calls_traced": stats.get(name, (0, 0))[0], "avg_us": round(stats.get(name, (0, 0.0))[1] / 1e3, 2)}
+        if (name, "FETCH_SIZE") in fetch and (name, "WRITE_SIZE") in write and ff and fw:
+            fk, wk = fetch[(name, "FETCH_SIZE")][1], write[(name, "WRITE_SIZE")][1]
+            e.update({"fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                      "hbm_bytes": int(fk * 1024 * ff + wk * 1024 * fw)})
+        if (name, "TCC_HIT_sum") in tcc and (name, "TCC_MISS_sum") in tcc:
+            hit, miss = tcc[(name, "TCC_HIT_sum")][1], tcc[(name, "TCC_MISS_sum")][1]
+            e["l2_hit_rate"] = round(hit / max(hit + miss, 1.0), 4)
+        kernels[name] = e
+    rec = {"workload": workload, "source_sha256": source_hash(),
+           "copy_probe": {"bytes_each_way": copy_bytes, "fetch_kib": ckf, "write_kib": ckw,
+                          "fetch_factor": ff, "write_factor": fw},
+           "kernels": kernels, "commands": PROFILE_COMMANDS}
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"{workload}_counters.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [f"# Kernel times and HBM traffic, {workload} synthetic connectome", "",
+             "Per-dispatch averages. Times: `rocprofv3 --kernel-trace --stats`. Bytes: `FETCH_SIZE` and",
+             "`WRITE_SIZE` (KiB per dispatch, separate runs), scaled by what the same counters read for a",
+             (f"plain 256 MiB device copy (`bench.py --copy-probe`): fetch x{ff:.3f}, write x{fw:.3f}." if ff and fw
+              else "plain 256 MiB device copy (`bench.py --copy-probe`): calibration missing."), "",
+             "| kernel | calls (trace) | avg us | FETCH KiB | WRITE KiB | HBM GB (scaled) | L2 hit |",
+             "|---|---|---|---|---|---|---|"]
+    for name, e in kernels.items():
+        gb = f"{e['hbm_bytes'] / 1e9:.3f}" if "hbm_bytes" in e else "-"
+        lines.append(f"| `{name}` | {e['calls_traced']} | {e['avg_us']} | {e.get('fetch_kib', '-')} | "
+                     f"{e.get('write_kib', '-')} | {gb} | {e.get('l2_hit_rate', '-')} |")
+    lines += ["", f"Library source SHA-256: `{rec['source_sha256']}`", "",
+              "Commands (repository root `$R`; run from `/tmp` with `TMPDIR=/tmp`,",
+              "`LIFE_SYNTH_CACHE=/tmp/life_synth`), then `python3 bench.py --summarize $R/gpurun_out/prof`:", ""]
+    lines += [f"    {c}" for c in PROFILE_COMMANDS.values()]
+    with open(os.path.join(out_dir, f"{workload}_kernels.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"summarized": workload, "kernels": list(kernels)}))
+
+
+def recorded_traffic(workload: str, kind: str):
+    """HBM bytes per launch of the kernel class from profiles/, or None when the
+    record is missing or was taken on other library sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != source_hash():
+        return None
+    for name, e in rec["kernels"].items():
+        if "hbm_bytes" in e and re.sub(r"<\d+>$", "", name) in KIND_KERNELS[kind][:1]:
+            return e["hbm_bytes"]
+    for name, e in rec["kernels"].items():
+        if "hbm_bytes" in e and re.sub(r"<\d+>$", "", name) in KIND_KERNELS[kind]:
+            return e["hbm_bytes"]
+    return None
 
 
 def algorithmic(kind: str, d) -> tuple[float, float]:
@@ -82,7 +209,12 @@ def main():
                     help="voxel processing order of the plan: Morton order of the grid coordinates, or voxel index")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (calibrates the HBM byte counters)")
+    ap.add_argument("--summarize", metavar="PROF_DIR",
+                    help="only summarize rocprofv3 outputs (trace/, fetch/, write/, tcc/, copyf/, copyw/) into profiles/")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.config)
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -165,7 +297,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(bw / HBM_PEAK_GBS, 4)}
-    roof.update({"traffic": None, "kernel": dom, "avg_ms": round(avg[dom], 4),
+    roof.update({"traffic": recorded_traffic(args.config, dom), "kernel": dom, "avg_ms": round(avg[dom], 4),
                  "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
                  "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})
 

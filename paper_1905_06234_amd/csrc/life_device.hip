@@ -49,6 +49,17 @@ struct Gate {
 };
 __device__ inline bool gated_off(const Gate &g) { return g.st && (int)(g.st->iter & 1) != g.par; }
 
+// Work item of this workgroup.  Consecutive workgroups are dispatched to the 8
+// XCDs in turn; this gives each XCD one contiguous range of items, so that
+// neighbouring chunks (or fascicle ranks) share that XCD's L2.  A bijection on
+// [0, gridDim.x).
+__device__ __forceinline__ int xcd_item()
+{
+    const int n = (int)gridDim.x, i = (int)blockIdx.x;
+    const int per = n >> 3, rem = n & 7, x = i & 7, k = i >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 constexpr int kBlock = 256;                  // threads per block of the generic / glue kernels
 constexpr int kSeg = 32;                     // lanes per voxel segment (generic kernels)
 constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block (generic kernels)
@@ -167,9 +178,9 @@ constexpr int kBatch = 64;                   // entries per batch: kGL steps
 // [q0 + kSE*E_j, q0 + kSE*E_{j+1}).
 struct WaveRange {
     int p[kWaveVoxels + 1];
-    __device__ __forceinline__ WaveRange(const int32_t *__restrict__ wave_work, int t, int T, int wave)
+    __device__ __forceinline__ WaveRange(const int32_t *__restrict__ wave_work, int chunk, int t, int T, int wave)
     {
-        const int32_t *ww = wave_work + ((size_t)(blockIdx.x * T + t) * kChunkWaves + wave) * life::kWorkInts;
+        const int32_t *ww = wave_work + ((size_t)(chunk * T + t) * kChunkWaves + wave) * life::kWorkInts;
         const int q0 = uni(ww[0]);
         p[0] = q0;
 #pragma unroll
@@ -217,6 +228,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     constexpr int ROW = NC * 32;
     constexpr int PER = NC * 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = xcd_item();
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         const int a0 = t * TA;
         __syncthreads();
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
-        const WaveRange R(wave_work, t, T, wave);
+        const WaveRange R(wave_work, chunk, t, T, wave);
         __syncthreads();
         if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
         // two-stage prefetch over batch starts: the scalars of batch i+2 and the
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
             x += __shfl_xor(x, 32, 64);
             acc[j][e] = x;
         }
-        const int v = uni(chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j]);
+        const int v = uni(chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + j]);
         if (v >= 0 && g == 0) {
             float *yv = y + (size_t)v * nth;
             const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
@@ -342,12 +354,13 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
     constexpr int ROW = NC * 32;
     constexpr int PER = NC * 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = xcd_item();
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;
     float yv[kWaveVoxels][PER];
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
-        const int v = uni(chunk_vox[blockIdx.x * kChunkVoxels + wave * kWaveVoxels + j]);
+        const int v = uni(chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + j]);
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
         const int a0 = t * TA;
         __syncthreads();
         stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
-        const WaveRange R(wave_work, t, T, wave);
+        const WaveRange R(wave_work, chunk, t, T, wave);
         __syncthreads();
         if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
         int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
@@ -543,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
 {
     if (gated_off(gate)) return;   // uniform over the grid
     const int lane = threadIdx.x & (kFasLanes - 1);
-    const int f = blockIdx.x * kFasPerBlock + threadIdx.x / kFasLanes;
+    const int f = xcd_item() * kFasPerBlock + threadIdx.x / kFasLanes;
     float s = 0.f;
     if (f < nf) {
         const int beg = fptr[f], end = fptr[f + 1];
