@@ -86,7 +86,9 @@ typedef enum {
     LIFE_K_WC_Z_2ND = 6,   /* WC pass 1 of v'' = M^T v' (SBB, gated by parity)    */
     LIFE_K_WC_SUM_2ND = 7, /* WC pass 2 of v'' (SBB, gated by parity)             */
     LIFE_K_PERMUTE = 8,    /* weights into the plan's fascicle order              */
-    LIFE_K_COUNT = 9
+    LIFE_K_DD = 9,         /* dictionary gradient (per-group partials)            */
+    LIFE_K_DD_REDUCE = 10, /* dictionary gradient: sum of the partials            */
+    LIFE_K_COUNT = 11
 } life_kernel_kind;
 
 /* Human-readable name of a status code (static string; never NULL). */
@@ -199,6 +201,19 @@ life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, 
  *   Other arguments, state and errors as life_sbbnnls_step. */
 life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D, const float *b, float *w,
                                      float *gt_prev, life_sbb_state *state, void *stream);
+
+/* Gradient with respect to the dictionary of the DSC product: with y = M(D) w
+ * (eq. 1, M_v = D Phi_v of eq. 3 with S0 folded into Phi; y is linear in D),
+ *   dD[t + N_theta*a] = d<ybar, M(D) w>/dD[t, a]
+ *                     = sum over nonzeros c with atom_c = a of
+ *                       phi_c * w[fascicle_c] * ybar[t + N_theta*voxel_c].
+ * With ybar = 2 (M w - y_obs) this is the dictionary gradient of the loss
+ * ||y_obs - M(D) w||^2; the weight gradient is life_wc of the same ybar.  The
+ * paper fits w only; this call serves dictionary learning over the same encoding.
+ *   w (device, N_f) and ybar (device, N_theta*N_v) are read; dD (device,
+ *   N_theta*N_a) is overwritten (atoms with no nonzero get 0).  Deterministic.
+ * Errors: as life_dsc. */
+life_status life_dict_grad(life_plan_t plan, const float *w, const float *ybar, float *dD, void *stream);
 
 /* Profiling hooks for the benchmark: when enabled, every kernel the plan
  * launches is bracketed by HIP events on its stream.  The two launches of an

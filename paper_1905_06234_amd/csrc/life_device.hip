@@ -583,6 +583,173 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
     if (part) block_sum_store<kBlock>(sq, part);
 }
 
+// ----------------------------------------------------------------------------- dictionary gradient
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kPsiStride = life::kPsiStride;
+
+// dD = d<ybar, M(D) w>/dD:  dD[:, a] = sum over nonzeros c with atom_c = a of
+// (phi_c w[f_c]) * ybar[:, voxel_c].  Per (chunk, atom tile) the nonzeros are
+// first merged into a dense block Psi[a][slot] = sum of phi_c w[f_c] over the
+// nonzeros of (voxel of slot, a) (LDS, fixed-order segmented sums); then
+// dD_tile += Ybar_chunk * Psi^T is a dense product over the chunk's 64 voxel slots
+// on the matrix cores (v_mfma_f32_16x16x4_f32, FP32 in, FP32 accumulate), with
+// Ybar_chunk staged in LDS as [theta][slot].
+// One workgroup owns one atom tile and one contiguous group of chunks; it keeps
+// its dD_tile share in the accumulators and writes it once to part (layout
+// [tile][group][atom of tile][theta, padded to 16]); k_dd_reduce sums the groups.
+//   MFMA operands (16 x 16 x 4 per instruction, 16 steps per chunk): lane l has
+//   row = l % 16, kq = l / 16; step s uses voxel slot 4 kq + s:
+//     A[row][kq] = Ybar[16 i + row][4 kq + s]   (theta block i)
+//     B[kq][row] = Psi[16 m + row][4 kq + s]    (atom block m)
+//   and the accumulator element r of lane l is (theta 16 i + 4 kq + r, atom 16 m + row).
+template <int NBW>
+__global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ chunk_vox,
+                                                  const int32_t *__restrict__ wave_work,
+                                                  const int16_t *__restrict__ atom,
+                                                  const int32_t *__restrict__ fas,
+                                                  const float *__restrict__ phi,
+                                                  const float *__restrict__ w,
+                                                  const float *__restrict__ ybar,
+                                                  float *__restrict__ part, int nth, int T, int TA, int TAP,
+                                                  int n_chunks, int G)
+{
+    extern __shared__ float4 lds4[];
+    float *psi = reinterpret_cast<float *>(lds4);
+    const int NTB = (nth + 15) / 16, NT16 = 16 * NTB;
+    float *ylds = psi + TAP * kPsiStride;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int item = xcd_item();
+    const int t = item % T, grp = item / T;
+    const int c0 = (int)((int64_t)grp * n_chunks / G), c1 = (int)((int64_t)(grp + 1) * n_chunks / G);
+    const int a0 = t * TA;
+    const int MB = TAP / 16, NB = NTB * MB;
+    const int b_lo = wave * NB / kChunkWaves, b_hi = (wave + 1) * NB / kChunkWaves;   // this wave's blocks
+    const int row = lane & 15, kq = lane >> 4;
+    f32x4 acc[NBW];
+#pragma unroll
+    for (int k = 0; k < NBW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int n4 = TAP * kPsiStride / 4;
+
+    for (int c = c0; c < c1; ++c) {
+        __syncthreads();                          // the previous chunk's products are done with the LDS
+        for (int i = threadIdx.x; i < n4; i += kWG) lds4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = threadIdx.x; i < kChunkVoxels * NT16; i += kWG) {
+            const int slot = i / NT16, th = i - slot * NT16;
+            const int v = chunk_vox[(size_t)c * kChunkVoxels + slot];
+            ylds[th * kPsiStride + slot] = (v >= 0 && th < nth) ? ybar[(size_t)v * nth + th] : 0.f;
+        }
+        __syncthreads();
+        // Psi of this chunk and tile: one nonzero per lane; atoms never decrease inside
+        // a slot's sub-range, so equal atoms form runs, summed by a segmented scan
+        {
+            const WaveRange R(wave_work, c, t, T, wave);
+#pragma unroll
+            for (int j = 0; j < kWaveVoxels; ++j) {
+                float *col = psi + wave * kWaveVoxels + j;
+                for (int b = R.p[j]; b < R.p[j + 1]; b += 64) {
+                    const int m = min(64, R.p[j + 1] - b);
+                    const bool valid = lane < m;
+                    const int q = valid ? b + lane : b;
+                    const int a = atom[q];
+                    float sv = valid ? phi[q] * w[fas[q]] : 0.f;
+                    const int key = valid ? a : -1;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const float so = __shfl_up(sv, o, 64);
+                        const int ko = __shfl_up(key, o, 64);
+                        if (lane >= o && ko == key) sv += so;
+                    }
+                    const int kn = __shfl_down(key, 1, 64);
+                    if (valid && (lane == 63 || kn != key)) col[(a - a0) * kPsiStride] += sv;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NBW; ++k) {
+            const int bb = b_lo + k;
+            if (bb < b_hi) {
+                const int i = bb / MB, mb = bb - i * MB;
+                const float4 *ap = reinterpret_cast<const float4 *>(ylds + (16 * i + row) * kPsiStride + 4 * kq);
+                const float4 *bp = reinterpret_cast<const float4 *>(psi + (16 * mb + row) * kPsiStride + 4 * kq);
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const float4 A = ap[h], B = bp[h];
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.x, B.x, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.y, B.y, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.z, B.z, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.w, B.w, acc[k], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *out = part + (size_t)(t * G + grp) * TAP * NT16;
+#pragma unroll
+    for (int k = 0; k < NBW; ++k) {
+        const int bb = b_lo + k;
+        if (bb < b_hi) {
+            const int i = bb / MB, mb = bb - i * MB;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(size_t)(16 * mb + row) * NT16 + 16 * i + 4 * kq + r] = acc[k][r];
+        }
+    }
+}
+
+// dD[theta + nth a] = sum over groups g (fixed order) of the partial of a's tile.
+__global__ __launch_bounds__(kBlock) void k_dd_reduce(const float *__restrict__ part, float *__restrict__ dD,
+                                                       int nth, int na, int TA, int TAP, int G)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)na * nth) return;
+    const int a = (int)(idx / nth), th = (int)(idx - (int64_t)a * nth);
+    const int t = a / TA, al = a - t * TA;
+    const int NT16 = ((nth + 15) / 16) * 16;
+    const float *p = part + ((size_t)t * G * TAP + al) * NT16 + th;
+    const size_t stride = (size_t)TAP * NT16;
+    float s = 0.f;
+    for (int g = 0; g < G; ++g) s += p[g * stride];
+    dD[idx] = s;
+}
+
+// Generic dictionary gradient (any N_theta): one block per atom over the atom's
+// nonzeros (atom-major copy), 8 segments of 32 lanes, NT theta slots per lane,
+// fixed-order combination of the segments.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_dd_atom(const int32_t *__restrict__ aptr,
+                                                     const int32_t *__restrict__ avox,
+                                                     const int32_t *__restrict__ afas,
+                                                     const float *__restrict__ aphi,
+                                                     const float *__restrict__ w,
+                                                     const float *__restrict__ ybar, float *__restrict__ dD,
+                                                     int nth, int na)
+{
+    __shared__ float sh[kBlock / kSeg][kSeg * NT];
+    const int a = blockIdx.x;
+    const int lane = threadIdx.x & (kSeg - 1), seg = threadIdx.x / kSeg;
+    float acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = 0.f;
+    const int beg = aptr[a], end = aptr[a + 1];
+    for (int e = beg + seg; e < end; e += kBlock / kSeg) {
+        const float sv = aphi[e] * w[afas[e]];
+        const float *yv = ybar + (size_t)avox[e] * nth;
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            const int th = lane + kSeg * i;
+            if (th < nth) acc[i] = fmaf(sv, yv[th], acc[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i) sh[seg][lane + kSeg * i] = acc[i];
+    __syncthreads();
+    for (int th = threadIdx.x; th < nth; th += kBlock) {
+        float sum = 0.f;
+        for (int k = 0; k < kBlock / kSeg; ++k) sum += sh[k][th];
+        dD[(size_t)a * nth + th] = sum;
+    }
+}
+
 // ----------------------------------------------------------------------------- SBB glue
 
 // g~_f = g_f unless w_f = 0 and g_f > 0 (the bound is active); partial ||g~||^2.
@@ -714,6 +881,13 @@ struct life_plan_s {
     float *g = nullptr, *gt = nullptr, *vpp = nullptr, *q = nullptr;  // [Nf]
     double *part = nullptr;       // 5 regions of part_stride
     int64_t part_stride = 0;
+    // dictionary gradient: chunked (per tile and chunk group partials) ...
+    int dd_groups = 0, dd_tap = 0, dd_nbw = 0;
+    float *dd_part = nullptr;     // [T][groups][dd_tap][16 ceil(Nt/16)]
+    // ... or generic (atom-major copy of the nonzeros)
+    int32_t *a_ptr = nullptr;     // [Na + 1]
+    int32_t *a_vox = nullptr, *a_fas = nullptr;   // [nnz] voxel, fascicle rank
+    float *a_phi = nullptr;       // [nnz]
     // profiling
     bool profile = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -748,7 +922,8 @@ void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->wave_work, p->atom_c, p->fas_c,
                     p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
-                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part};
+                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
+                    p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -799,6 +974,27 @@ life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
     default: KERNEL<32><<<__VA_ARGS__; break;                                        \
     }
 
+// accumulator blocks per wave of the dictionary-gradient kernel (at most 10 for
+// the tile geometries of N_theta <= 128: e.g. 6 theta blocks x 26 atom blocks
+// over 16 waves)
+int dd_nbw_variant(int need)
+{
+    static const int variants[] = {1, 2, 3, 5, 9, 12};
+    for (int v : variants)
+        if (v >= need) return v;
+    return -1;
+}
+
+#define LIFE_DISPATCH_NBW(NBWV, KERNEL, ...)                                         \
+    switch (NBWV) {                                                                  \
+    case 1: KERNEL<1><<<__VA_ARGS__; break;                                          \
+    case 2: KERNEL<2><<<__VA_ARGS__; break;                                          \
+    case 3: KERNEL<3><<<__VA_ARGS__; break;                                          \
+    case 5: KERNEL<5><<<__VA_ARGS__; break;                                          \
+    case 9: KERNEL<9><<<__VA_ARGS__; break;                                          \
+    default: KERNEL<12><<<__VA_ARGS__; break;                                        \
+    }
+
 #define LIFE_DISPATCH_NC(NCV, KERNEL, ...)                                           \
     switch (NCV) {                                                                   \
     case 1: KERNEL<1><<<__VA_ARGS__; break;                                          \
@@ -823,7 +1019,9 @@ hipError_t allow_lds()
     const int bytes = life::kLdsBudget;
     const void *fns[] = {(const void *)k_dsc_chunk<1>, (const void *)k_dsc_chunk<2>, (const void *)k_dsc_chunk<3>,
                          (const void *)k_dsc_chunk<4>, (const void *)k_wcz_chunk<1>, (const void *)k_wcz_chunk<2>,
-                         (const void *)k_wcz_chunk<3>, (const void *)k_wcz_chunk<4>};
+                         (const void *)k_wcz_chunk<3>, (const void *)k_wcz_chunk<4>, (const void *)k_dd_chunk<1>,
+                         (const void *)k_dd_chunk<2>, (const void *)k_dd_chunk<3>, (const void *)k_dd_chunk<5>,
+                         (const void *)k_dd_chunk<9>, (const void *)k_dd_chunk<12>};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -903,6 +1101,30 @@ life_status enqueue_gather(life_plan_s *p, const float *w, hipStream_t s)
     });
 }
 
+// dD from w_rank (weights already in rank order) and ybar.
+life_status enqueue_dd(life_plan_s *p, const float *ybar, float *dD, hipStream_t s)
+{
+    const life_dims &d = p->dims;
+    const int nth = d.n_theta, na = d.n_atoms;
+    if (chunked(p)) {
+        const int T = p->tile.n_tiles, TA = p->tile.tile_atoms, TAP = p->dd_tap, G = p->dd_groups;
+        const size_t lds = (size_t)(TAP + (nth + 15) / 16 * 16) * kPsiStride * sizeof(float);
+        life_status st = launch(p, LIFE_K_DD, s, [&] {
+            LIFE_DISPATCH_NBW(p->dd_nbw, k_dd_chunk, T * G, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+                                                                         p->fas_c, p->phi_c, p->w_rank, ybar,
+                                                                         p->dd_part, nth, T, TA, TAP, p->n_chunks, G))
+        });
+        if (st != LIFE_OK) return st;
+        return launch(p, LIFE_K_DD_REDUCE, s, [&] {
+            k_dd_reduce<<<cdiv((int64_t)na * nth, kBlock), kBlock, 0, s>>>(p->dd_part, dD, nth, na, TA, TAP, G);
+        });
+    }
+    return launch(p, LIFE_K_DD, s, [&] {
+        LIFE_DISPATCH_SLOTS(p->slots, k_dd_atom, na, kBlock, 0, s>>>(p->a_ptr, p->a_vox, p->a_fas, p->a_phi,
+                                                                     p->w_rank, ybar, dD, nth, na))
+    });
+}
+
 }  // namespace
 
 // ============================================================================= C ABI
@@ -925,6 +1147,8 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
     std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, ppos, pvox, vdsc;
+    std::vector<int32_t> aptr, avox, afas;
+    std::vector<float> aphi;
     std::vector<int16_t> atom_v, atom_c;
     std::vector<int32_t> fas_v, fas_c;
     std::vector<float> phi_v, phi_c;
@@ -956,6 +1180,22 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
             phi_v[(size_t)p] = phi[c];
             vdsc[(size_t)p] = voxel[c];
         }
+        if (n_chunks == 0 && d.nnz > 0) {
+            // atom-major copy of the nonzeros for the generic dictionary gradient
+            aptr.assign((size_t)d.n_atoms + 1, 0);
+            for (int64_t q = 0; q < d.nnz; ++q) ++aptr[(size_t)atom_v[(size_t)q] + 1];
+            for (int32_t a = 0; a < d.n_atoms; ++a) aptr[(size_t)a + 1] += aptr[(size_t)a];
+            std::vector<int32_t> fill(aptr.begin(), aptr.end() - 1);
+            avox.resize((size_t)d.nnz);
+            afas.resize((size_t)d.nnz);
+            aphi.resize((size_t)d.nnz);
+            for (int64_t q = 0; q < d.nnz; ++q) {
+                const int32_t e = fill[(size_t)atom_v[(size_t)q]]++;
+                avox[(size_t)e] = vdsc[(size_t)q];
+                afas[(size_t)e] = fas_v[(size_t)q];
+                aphi[(size_t)e] = phi_v[(size_t)q];
+            }
+        }
         if (n_chunks > 0) {
             tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
             cvox.resize((size_t)n_chunks * kChunkVoxels);
@@ -984,6 +1224,20 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
     p->part_stride = nb;
+    int64_t dd_floats = 0;
+    if (n_chunks > 0) {
+        const int T = tg.n_tiles;
+        p->dd_tap = (tg.tile_atoms + 15) / 16 * 16;
+        p->dd_groups = std::max(1, std::min(n_chunks, 512 / T));
+        const int nb_blocks = (d.n_theta + 15) / 16 * (p->dd_tap / 16);
+        p->dd_nbw = dd_nbw_variant((nb_blocks + kChunkWaves - 1) / kChunkWaves);
+        dd_floats = (int64_t)T * p->dd_groups * p->dd_tap * ((d.n_theta + 15) / 16 * 16);
+        if (p->dd_nbw < 0 ||
+            (int64_t)(p->dd_tap + (d.n_theta + 15) / 16 * 16) * kPsiStride * 4 > life::kLdsBudget) {
+            delete p;
+            return LIFE_EINVAL;   // cannot happen: tiles hold at most kMaxTileAtoms atoms
+        }
+    }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     chk(dalloc(&p->vox_ptr, d.n_voxels + 1));
@@ -1010,6 +1264,11 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     chk(dalloc(&p->vpp, d.n_fascicles));
     chk(dalloc(&p->q, d.n_fascicles));
     chk(dalloc(&p->part, 5 * nb));
+    chk(dalloc(&p->dd_part, dd_floats));
+    chk(dalloc(&p->a_ptr, (int64_t)aptr.size()));
+    chk(dalloc(&p->a_vox, (int64_t)avox.size()));
+    chk(dalloc(&p->a_fas, (int64_t)afas.size()));
+    chk(dalloc(&p->a_phi, (int64_t)aphi.size()));
     if (e == hipSuccess && n_chunks > 0) e = allow_lds();
     if (e != hipSuccess) {
         free_plan(p);
@@ -1033,6 +1292,10 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());
     up(p->wc_perm, wperm.data(), sizeof(int32_t) * wperm.size());
+    up(p->a_ptr, aptr.data(), sizeof(int32_t) * aptr.size());
+    up(p->a_vox, avox.data(), sizeof(int32_t) * avox.size());
+    up(p->a_fas, afas.data(), sizeof(int32_t) * afas.size());
+    up(p->a_phi, aphi.data(), sizeof(float) * aphi.size());
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_plan(p);
@@ -1192,6 +1455,21 @@ extern "C" life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
     return enqueue_sbb(plan, D, b, w, gt_prev, state, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_dict_grad(life_plan_t plan, const float *w, const float *ybar, float *dD, void *stream)
+{
+    if (!plan) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(w, d.n_fascicles) || !need(ybar, (int64_t)d.n_theta * d.n_voxels) ||
+        !need(dD, (int64_t)d.n_theta * d.n_atoms))
+        return LIFE_EINVAL;
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    life_status st = enqueue_gather(plan, w, s);
+    if (st != LIFE_OK) return st;
+    return enqueue_dd(plan, ybar, dD, s);
 }
 
 extern "C" life_status life_profile_enable(life_plan_t plan, int enable)

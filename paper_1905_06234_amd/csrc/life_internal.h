@@ -36,6 +36,12 @@ constexpr int kWaveVoxels = 4;
 constexpr int kChunkVoxels = kChunkWaves * kWaveVoxels;
 constexpr int kMaxTileRowFloats = 128;      // chunked kernels handle n_theta <= 128
 constexpr int kLdsBudget = 160 * 1024 - 1024;
+// Dictionary-gradient kernel: per tile, a dense (atom x voxel slot) block of the
+// chunk and the chunk's (theta x voxel slot) signal block in LDS, rows of
+// kPsiStride floats (64 slots + 4 to spread the banks); a tile has at most
+// kMaxTileAtoms atoms so that both fit the LDS budget for every N_theta <= 128.
+constexpr int kPsiStride = 68;
+constexpr int kMaxTileAtoms = 512;
 
 struct TileGeom {
     int row_floats = 0;   // LDS row length (floats), 0 = chunked kernels not applicable
@@ -56,7 +62,8 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
 // padded arrays holds the tile-t sub-ranges of the wave's voxel slots j = 0..3,
 // each padded with zero-valued entries to a multiple of kStepEntries (one step of
 // the wave's lane groups never mixes voxels); chunks are laid out one after the
-// other.
+// other.  Inside a slot's sub-range the atoms never decrease: entries follow the
+// DSC order and the pads repeat the last atom.
 // wave_work[((c*T + t)*kChunkWaves + w)*kWorkInts + k]:
 //   k = 0: first position of the range; k = 1..4: cumulative step counts E1..E4
 //   (slot j owns steps [E_j, E_{j+1}), E_0 = 0; kStepEntries entries per step).
@@ -66,7 +73,7 @@ int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile
                      int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
 
 // The padded arrays of the chunked layout from the canonical DSC-order arrays:
-// pad entries get value 0, an atom of their tile and fascicle rank 0.  The WC
+// pad entries get value 0, the atom of the entry before them and fascicle rank 0.  The WC
 // pass-1 output z uses its own order inside each chunk's range: the chunk's
 // entries in WC order (so one fascicle's entries in one chunk are adjacent),
 // then its pad entries.  z_pos[q] = z position of padded entry q;

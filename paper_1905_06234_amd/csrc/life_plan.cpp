@@ -187,7 +187,7 @@ TileGeom tile_geometry(int n_theta, int n_atoms)
     TileGeom g;
     const int row = ((n_theta + 31) / 32) * 32;
     if (row > kMaxTileRowFloats) return g;
-    const int max_atoms = kLdsBudget / (row * 4);
+    const int max_atoms = std::min(kLdsBudget / (row * 4), kMaxTileAtoms);
     const int n_tiles = (n_atoms + max_atoms - 1) / max_atoms;
     g.row_floats = row;
     g.n_tiles = n_tiles;
@@ -275,19 +275,26 @@ int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, con
     atom_c.assign((size_t)n_pad, 0);
     fas_c.assign((size_t)n_pad, 0);
     phi_c.assign((size_t)n_pad, 0.f);
-    for (int c = 0; c < n_chunks; ++c)
-        for (int t = 0; t < T; ++t)
-            for (int w = 0; w < kChunkWaves; ++w) {
-                const int32_t *ww = &wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
-                for (int64_t q = ww[0]; q < ww[0] + kStepEntries * (int64_t)ww[kWaveVoxels]; ++q)
-                    atom_c[(size_t)q] = static_cast<int16_t>(t * tg.tile_atoms);
-            }
     for (int64_t p = 0; p < d->nnz; ++p) {
         const size_t q = (size_t)cpos[(size_t)p];
         atom_c[q] = atom_v[p];
         fas_c[q] = fas_v[p];
         phi_c[q] = phi_v[p];
     }
+    // pads (the tail of each slot's sub-range) repeat the atom before them
+    for (int c = 0; c < n_chunks; ++c)
+        for (int t = 0; t < T; ++t)
+            for (int w = 0; w < kChunkWaves; ++w) {
+                const int32_t *ww = &wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
+                for (int j = 0; j < kWaveVoxels; ++j) {
+                    const int v = chunk_vox[(size_t)c * kChunkVoxels + w * kWaveVoxels + j];
+                    if (v < 0) continue;
+                    const int64_t beg = ww[0] + (int64_t)kStepEntries * (j ? ww[j] : 0);
+                    const int64_t end = ww[0] + (int64_t)kStepEntries * ww[j + 1];
+                    const int64_t n_real = tile_ptr[(size_t)v * (T + 1) + t + 1] - tile_ptr[(size_t)v * (T + 1) + t];
+                    for (int64_t q = beg + n_real; q < end; ++q) atom_c[(size_t)q] = atom_c[(size_t)q - 1];
+                }
+            }
     // z order: inside each chunk's range, its entries in WC order, then its pads
     std::vector<int64_t> next((size_t)n_chunks + 1);
     for (int c = 0; c < n_chunks; ++c) next[c] = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];

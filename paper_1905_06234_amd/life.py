@@ -19,7 +19,8 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblife.so")
 
-KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_2nd", "wc_sum_2nd", "permute")
+KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_2nd", "wc_sum_2nd", "permute", "dd",
+           "dd_reduce")
 STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
 STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
 
@@ -54,6 +55,7 @@ _SIGS = {
     "life_wc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_sbbnnls_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "life_sbbnnls_step_lagged": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "life_dict_grad": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "life_profile_read": (ctypes.c_int, [_P, _P, _P]),
 }
@@ -222,6 +224,18 @@ class Plan:
         _check("life_wc", load().life_wc(self._h, self._d(D), _dev_f32(y, self.n_signal, "y"),
                                          _dev_f32(g, self.dims.n_fascicles, "g"), _stream(stream, y.device)))
         return g
+
+    def dict_grad(self, w, ybar, dD=None, stream=None):
+        """dD = d<ybar, M(D) w>/dD, shape (n_atoms, n_theta) like D (life_dict_grad)."""
+        torch = _torch()
+        d = self.dims
+        if dD is None:
+            dD = torch.empty((d.n_atoms, d.n_theta), dtype=torch.float32, device=ybar.device)
+        _check("life_dict_grad", load().life_dict_grad(self._h, _dev_f32(w, d.n_fascicles, "w"),
+                                                       _dev_f32(ybar, self.n_signal, "ybar"),
+                                                       _dev_f32(dD, d.n_theta * d.n_atoms, "dD"),
+                                                       _stream(stream, ybar.device)))
+        return dD
 
     @staticmethod
     def _state(state):
