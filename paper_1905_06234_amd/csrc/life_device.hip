@@ -70,9 +70,9 @@ constexpr int kAlphaThreads = 1024;
 
 // ----------------------------------------------------------------------------- device helpers
 
-// Sum a double over the block in a fixed order and store it at out[blockIdx.x].
+// Sum a double over the block in a fixed order and store it at out[slot].
 template <int NT>
-__device__ __forceinline__ void block_sum_store(double v, double *out)
+__device__ __forceinline__ void block_sum_store(double v, double *out, int slot)
 {
     __shared__ double sh[NT / 64];
 #pragma unroll
@@ -83,7 +83,7 @@ __device__ __forceinline__ void block_sum_store(double v, double *out)
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NT / 64; ++i) s += sh[i];
-        out[blockIdx.x] = s;
+        out[slot] = s;
     }
 }
 
@@ -146,13 +146,13 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 template <int CTRL>
 __device__ __forceinline__ float dppf(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 // broadcast lane K of every row to the row (row_newbcast)
 template <int K>
 __device__ __forceinline__ int bcast16(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x150 + K, 0xf, 0xf, true);
 }
 template <int K>
 __device__ __forceinline__ float bcast16f(float x) { return dppf<0x150 + K>(x); }
@@ -212,7 +212,8 @@ struct WaveRange {
 // DSC: y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
 // NC = 32-float chunks per LDS row (N_theta <= 32 NC).
 template <int NC>
-__global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_vox,
+__global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_map,
+                                                   const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
                                                    const int32_t *__restrict__ fas,
@@ -227,8 +228,9 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
     constexpr int PER = NC * 2;
+    const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
+    if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int chunk = xcd_item();
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
                 }
         }
     }
-    if (part) block_sum_store<kWG>(sq, part);
+    if (part) block_sum_store<kWG>(sq, part, chunk);
 }
 
 // WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the
@@ -338,7 +340,8 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
 // chunk's own range, in WC order, so pass 2 reads one fascicle's values in a chunk
 // as one contiguous run.
 template <int NC>
-__global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_vox,
+__global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_map,
+                                                   const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
                                                    const float *__restrict__ phi,
@@ -353,8 +356,9 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
     constexpr int PER = NC * 2;
+    const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
+    if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int chunk = xcd_item();
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;
     float yv[kWaveVoxels][PER];
@@ -378,17 +382,18 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
         __syncthreads();
         if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
         int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
-        int a_n = atom[ix];
+        int a_n = atom[ix], zp_n = z_pos[ix];
         float ph_n = phi[ix];
 #pragma unroll
         for (int j = 0; j < kWaveVoxels; ++j) {
             for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
                 const int m = min(kBatch, R.p[j + 1] - b);
-                const int a_c = a_n;
+                const int a_c = a_n, zp_c = zp_n;
                 const float ph_c = ph_n;
                 int nxt = b + kBatch < R.p[j + 1] ? b + kBatch : R.p[j + 1];
                 nxt = nxt + mypos < R.p[kWaveVoxels] ? nxt + mypos : R.p[0];
                 a_n = atom[nxt];
+                zp_n = z_pos[nxt];
                 ph_n = phi[nxt];
                 const bool valid = mypos < m;
                 const int aoff = valid ? (a_c - a0) * ROW : 0;
@@ -432,7 +437,7 @@ __global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ c
     }
                 LIFE_TR_STAGE(8) LIFE_TR_STAGE(4) LIFE_TR_STAGE(2) LIFE_TR_STAGE(1)
 #undef LIFE_TR_STAGE
-                if (valid) z[z_pos[b + mypos]] = ph_c * p[0];
+                if (valid) z[zp_c] = ph_c * p[0];
             }
         }
     }
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_dsc(const int32_t *__restrict__ vptr
             }
         }
     }
-    if (part) block_sum_store<kBlock>(sq, part);
+    if (part) block_sum_store<kBlock>(sq, part, blockIdx.x);
 }
 
 // WC pass 1 (generic): z[c] = phi_c * <D[:, atom_c], y[:, v]>, 32 lanes per voxel.
@@ -580,12 +585,13 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
         g[gmap ? gmap[f] : f] = s;
         sq = (double)s * (double)s;
     }
-    if (part) block_sum_store<kBlock>(sq, part);
+    if (part) block_sum_store<kBlock>(sq, part, blockIdx.x);
 }
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ----------------------------------------------------------------------------- dictionary gradient
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kPsiStride = life::kPsiStride;
 
 // dD = d<ybar, M(D) w>/dD:  dD[:, a] = sum over nonzeros c with atom_c = a of
@@ -599,9 +605,10 @@ constexpr int kPsiStride = life::kPsiStride;
 // its dD_tile share in the accumulators and writes it once to part (layout
 // [tile][group][atom of tile][theta, padded to 16]); k_dd_reduce sums the groups.
 //   MFMA operands (16 x 16 x 4 per instruction, 16 steps per chunk): lane l has
-//   row = l % 16, kq = l / 16; step s uses voxel slot 4 kq + s:
-//     A[row][kq] = Ybar[16 i + row][4 kq + s]   (theta block i)
-//     B[kq][row] = Psi[16 m + row][4 kq + s]    (atom block m)
+//   row = l % 16, kq = l / 16; at step s the reduction index kq stands for voxel
+//   slot 16 kq + s, so the 16 steps cover the 64 slots once:
+//     A[row][kq] = Ybar[16 i + row][16 kq + s]   (theta block i)
+//     B[kq][row] = Psi[16 m + row][16 kq + s]    (atom block m)
 //   and the accumulator element r of lane l is (theta 16 i + 4 kq + r, atom 16 m + row).
 template <int NBW>
 __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ chunk_vox,
@@ -671,8 +678,8 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
             const int bb = b_lo + k;
             if (bb < b_hi) {
                 const int i = bb / MB, mb = bb - i * MB;
-                const float4 *ap = reinterpret_cast<const float4 *>(ylds + (16 * i + row) * kPsiStride + 4 * kq);
-                const float4 *bp = reinterpret_cast<const float4 *>(psi + (16 * mb + row) * kPsiStride + 4 * kq);
+                const float4 *ap = reinterpret_cast<const float4 *>(ylds + (16 * i + row) * kPsiStride + 16 * kq);
+                const float4 *bp = reinterpret_cast<const float4 *>(psi + (16 * mb + row) * kPsiStride + 16 * kq);
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
                     const float4 A = ap[h], B = bp[h];
@@ -764,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_mask(const float *__restrict__ w, co
         gt[i] = v;
         sq = (double)v * (double)v;
     }
-    block_sum_store<kBlock>(sq, part);
+    block_sum_store<kBlock>(sq, part, blockIdx.x);
 }
 
 // alpha from the partial sums; records the state; i += 1.
@@ -817,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_lag_q(const float *__restrict__ gt_p
         q[i] = v;
         sq = (double)v * (double)v;
     }
-    block_sum_store<kBlock>(sq, part);
+    block_sum_store<kBlock>(sq, part, blockIdx.x);
 }
 
 // w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.  The
@@ -862,6 +869,8 @@ struct life_plan_s {
     // chunked layout (see life::chunk_layout): padded copies of the DSC-order arrays
     int64_t n_pad = 0;
     int32_t *chunk_vox = nullptr; // [n_chunks * kChunkVoxels]
+    int32_t *chunk_map = nullptr; // [chunk_grid] chunk of each workgroup of the chunk kernels, -1 = none
+    int chunk_grid = 0;
     int32_t *wave_work = nullptr; // [n_chunks * n_tiles * kChunkWaves * kWorkInts]
     int16_t *atom_c = nullptr;    // [n_pad]
     int32_t *fas_c = nullptr;     // [n_pad]
@@ -920,7 +929,7 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_plan(life_plan_s *p)
 {
-    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->wave_work, p->atom_c, p->fas_c,
+    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c, p->fas_c,
                     p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
                     p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
                     p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi};
@@ -1043,7 +1052,8 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
         const int nc = p->tile.row_floats / 32;
         const size_t lds = tile_lds_bytes(p);
         return launch(p, LIFE_K_DSC, s, [&] {
-            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->chunk_grid, kWG, lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work,
+                                                                           p->atom_c,
                                                                            p->fas_c, p->phi_c, w, D, bsub, y, part,
                                                                            nth, p->dims.n_atoms, p->tile.n_tiles,
                                                                            p->tile.tile_atoms, vec_tile(p, D)))
@@ -1067,7 +1077,8 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
             const int nc = p->tile.row_floats / 32;
             const size_t lds = tile_lds_bytes(p);
             st = launch(p, kind, s, [&] {
-                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->n_chunks, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->chunk_grid, kWG, lds, s>>>(p->chunk_map, p->chunk_vox,
+                                                                               p->wave_work, p->atom_c,
                                                                                p->phi_c, p->z_pos, D, y, p->z, nth,
                                                                                p->dims.n_atoms, p->tile.n_tiles,
                                                                                p->tile.tile_atoms, vec_tile(p, D),
@@ -1147,7 +1158,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
     std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, ppos, pvox, vdsc;
-    std::vector<int32_t> aptr, avox, afas;
+    std::vector<int32_t> aptr, avox, afas, cmap;
     std::vector<float> aphi;
     std::vector<int16_t> atom_v, atom_c;
     std::vector<int32_t> fas_v, fas_c;
@@ -1204,6 +1215,13 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
                                          fas_v.data(), phi_v.data(), vdsc.data(), wperm.data(), wwork, atom_c,
                                          fas_c, phi_c, zpos, wperm_z);
             if (n_pad < 0) return LIFE_ERANGE;
+            std::vector<int64_t> work((size_t)n_chunks);
+            const size_t per_chunk = (size_t)tg.n_tiles * kChunkWaves * life::kWorkInts;
+            for (int c = 0; c < n_chunks; ++c) {
+                const int64_t end = c + 1 < n_chunks ? wwork[(size_t)(c + 1) * per_chunk] : n_pad;
+                work[(size_t)c] = end - wwork[(size_t)c * per_chunk];
+            }
+            cmap = life::chunk_schedule(work, life::kScheduleDefault);
         }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;
@@ -1220,6 +1238,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     p->tile = tg;
     p->n_chunks = n_chunks;
     p->n_pad = n_pad;
+    p->chunk_grid = (int)cmap.size();
     const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
@@ -1245,6 +1264,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     chk(dalloc(&p->fas_v, d.nnz));
     chk(dalloc(&p->phi_v, d.nnz));
     chk(dalloc(&p->chunk_vox, (int64_t)cvox.size()));
+    chk(dalloc(&p->chunk_map, (int64_t)cmap.size()));
     chk(dalloc(&p->wave_work, (int64_t)wwork.size()));
     chk(dalloc(&p->atom_c, n_pad));
     chk(dalloc(&p->fas_c, n_pad));
@@ -1282,6 +1302,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
     up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
     up(p->chunk_vox, cvox.data(), sizeof(int32_t) * cvox.size());
+    up(p->chunk_map, cmap.data(), sizeof(int32_t) * cmap.size());
     up(p->wave_work, wwork.data(), sizeof(int32_t) * wwork.size());
     up(p->atom_c, atom_c.data(), sizeof(int16_t) * atom_c.size());
     up(p->fas_c, fas_c.data(), sizeof(int32_t) * fas_c.size());

@@ -27,7 +27,8 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
 
 // Work decomposition of the chunked (LDS-tiled) kernels, computed on the host.
 //   The dictionary is staged in shared memory one atom tile at a time: n_tiles
-//   tiles of tile_atoms atoms, each row padded to row_floats (a multiple of 32).
+//   tiles of tile_atoms atoms (at most kMaxTileAtoms), each row padded to
+//   row_floats (a multiple of 32).
 //   Voxels are cut into chunks of kChunkVoxels consecutive voxels of the
 //   processing order; a chunk is one workgroup of kChunkWaves waves and each
 //   wave owns up to kWaveVoxels voxels.
@@ -71,6 +72,18 @@ constexpr int kStepEntries = 4;
 constexpr int kWorkInts = 5;
 int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
                      int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
+
+// Workgroup-to-chunk map of the chunked kernels (chunk or -1 per workgroup).
+// Consecutive workgroups are dispatched to the 8 XCDs in turn, so workgroup i
+// runs on XCD i % 8.  Policies: index order (workgroup i = chunk i); equal
+// counts (XCD x gets one contiguous run of n/8 chunks); equal work (XCD x gets
+// one contiguous run of chunks holding about 1/8 of the padded entries; the
+// runs' lengths differ, shorter ones are filled with -1).  Contiguous runs keep
+// neighbouring chunks, which gather nearby weights, on one L2.
+enum SchedulePolicy { kScheduleIndex = 0, kScheduleXcdCount = 1, kScheduleXcdWork = 2 };
+constexpr SchedulePolicy kScheduleDefault = kScheduleIndex;
+constexpr int kXcds = 8;
+std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePolicy policy);
 
 // The padded arrays of the chunked layout from the canonical DSC-order arrays:
 // pad entries get value 0, the atom of the entry before them and fascicle rank 0.  The WC

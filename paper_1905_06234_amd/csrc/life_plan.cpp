@@ -260,6 +260,41 @@ int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile
     return q;
 }
 
+std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePolicy policy)
+{
+    const int n = static_cast<int>(work.size());
+    std::vector<int32_t> map;
+    if (policy == kScheduleIndex || n < kXcds) {
+        map.resize((size_t)n);
+        for (int i = 0; i < n; ++i) map[(size_t)i] = i;
+        return map;
+    }
+    int bound[kXcds + 1];
+    if (policy == kScheduleXcdCount) {
+        const int per = n / kXcds, rem = n % kXcds;
+        bound[0] = 0;
+        for (int x = 0; x < kXcds; ++x) bound[x + 1] = bound[x] + per + (x < rem ? 1 : 0);
+    } else {
+        int64_t total = 0;
+        for (int64_t wk : work) total += wk;
+        bound[0] = 0;
+        bound[kXcds] = n;
+        int c = 0;
+        int64_t acc = 0;
+        for (int x = 1; x < kXcds; ++x) {
+            const int64_t target = total * x / kXcds;
+            while (c < n && acc + work[(size_t)c] <= target) acc += work[(size_t)c++];
+            bound[x] = c;
+        }
+    }
+    int len = 0;
+    for (int x = 0; x < kXcds; ++x) len = std::max(len, bound[x + 1] - bound[x]);
+    map.assign((size_t)len * kXcds, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (int k = 0; k < bound[x + 1] - bound[x]; ++k) map[(size_t)k * kXcds + x] = bound[x] + k;
+    return map;
+}
+
 int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
                        const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
                        const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
