@@ -139,6 +139,52 @@ life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32
                          const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
                          life_plan_t *out);
 
+/* A batched plan: n_inst independent problems that share the dictionary D,
+ * given as one block-diagonal problem.  The caller concatenates the instances:
+ * instance k owns voxels [vox_off[k], vox_off[k+1]) and fascicles
+ * [fas_off[k], fas_off[k+1]) of the union (dims describes the union); every
+ * nonzero's voxel and fascicle belong to the same instance.  One launch of each
+ * product then covers all instances; no work chunk spans two instances, so
+ * life_sbbnnls_step_batch can keep separate step lengths.  D, w, y, b and g are
+ * the concatenations of the instances' vectors.
+ *   vox_off, fas_off (host, n_inst + 1 entries: 0 = first, last = union size).
+ *   Other arguments as life_plan_ex (voxel_xyz optional, Morton order inside
+ *   each instance).
+ * Errors: LIFE_EINVAL (bad offsets, n_inst < 1, N_theta > 128 with n_inst > 1),
+ * LIFE_ERANGE (an index out of range or a nonzero that crosses instances),
+ * LIFE_ENOMEM, LIFE_EDEVICE. */
+life_status life_plan_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off, const int32_t *fas_off,
+                            const int16_t *atom, const int32_t *voxel, const int32_t *fascicle, const float *phi,
+                            const int16_t *voxel_xyz, life_plan_t *out);
+
+/* The restructuring of a batched plan on the host only (no device touched):
+ * voxel processing positions (proc_pos, host, n_voxels: instance by instance,
+ * each instance's block padded to whole 64-voxel chunks; Morton order inside an
+ * instance when voxel_xyz is given, else voxel order), and the permutations and
+ * offsets of life_plan_host over the union, with fascicles ranked by the mean
+ * processing position of their voxels and those without nonzeros ranked at the
+ * end of their own instance (so each instance's ranks are one contiguous
+ * block).  Arguments and errors as life_plan_batch / life_plan_host; any output
+ * may be NULL. */
+life_status life_plan_host_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                                 const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                                 const int32_t *fascicle, const int16_t *voxel_xyz, int32_t *proc_pos,
+                                 int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm,
+                                 int32_t *fas_ptr);
+
+/* Number of instances of a plan (1 unless built by life_plan_batch). */
+life_status life_plan_instances(life_plan_t plan, int32_t *n_inst);
+
+/* Choose the plan's work schedule by measurement (the paper selects its
+ * kernels by timing runs on the input, Sec. 4.1): every workgroup-to-chunk
+ * schedule (index order; XCD-contiguous ranges of equal count; of equal work)
+ * times reps DSC+WC pairs on (D, w, y) and the fastest is kept.  Results do
+ * not depend on the schedule.  D, w, y: device inputs as life_dsc/life_wc.
+ * policy (host, optional): the chosen schedule (0, 1, 2).  Synchronizes the
+ * device; uses the plan's workspace. */
+life_status life_plan_tune(life_plan_t plan, const float *D, const float *w, const float *y, int32_t reps,
+                           int32_t *policy);
+
 /* Release a plan and its device memory (synchronizes the device first).
  * NULL is accepted and ignored. */
 life_status life_plan_destroy(life_plan_t plan);
@@ -214,6 +260,17 @@ life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D, const flo
  *   N_theta*N_a) is overwritten (atoms with no nonzero get 0).  Deterministic.
  * Errors: as life_dsc. */
 life_status life_dict_grad(life_plan_t plan, const float *w, const float *ybar, float *dD, void *stream);
+
+/* One SBB-NNLS iteration (Algorithm 1, as life_sbbnnls_step) of every instance
+ * of a batched plan, in one pass of each product over all instances.  Each
+ * instance k has its own step length and scalars in states[k] (device,
+ * n_inst entries); the instances advance together (the second WC runs on the
+ * iterations where states[0].iter is even).  D (device), b (device, union
+ * signal) are read; w (device, union weights) is updated in place.  A plan with
+ * one instance takes the same path (its scalars summed per instance).
+ * Errors: as life_sbbnnls_step. */
+life_status life_sbbnnls_step_batch(life_plan_t plan, const float *D, const float *b, float *w,
+                                    life_sbb_state *states, void *stream);
 
 /* Profiling hooks for the benchmark: when enabled, every kernel the plan
  * launches is bracketed by HIP events on its stream.  The two launches of an

@@ -827,6 +827,89 @@ __global__ __launch_bounds__(kBlock) void k_lag_q(const float *__restrict__ gt_p
     block_sum_store<kBlock>(sq, part, blockIdx.x);
 }
 
+// Batched plans: the SBB scalars of every instance (one block per instance, all
+// instances at the same iteration; Algorithm 1).  y-space sums come from the
+// per-chunk partials of the instance's chunks, w-space sums are taken from the
+// vectors over the instance's rank range; every sum has a fixed order.
+__device__ double block_sum_range(const double *a, int lo, int hi)
+{
+    __shared__ double sh[kAlphaThreads];
+    double s = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += kAlphaThreads) s += a[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kAlphaThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_sumsq_range(const float *x, int lo, int hi)
+{
+    __shared__ double sh[kAlphaThreads];
+    double s = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += kAlphaThreads) s += (double)x[i] * (double)x[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kAlphaThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kAlphaThreads) void k_alpha_batch(const double *__restrict__ p_r,
+                                                                const double *__restrict__ p_vp,
+                                                                const int32_t *__restrict__ inst_chunk,
+                                                                const float *__restrict__ gt,
+                                                                const float *__restrict__ vpp,
+                                                                const int32_t *__restrict__ inst_rank,
+                                                                life_sbb_state *__restrict__ states)
+{
+    const int k = blockIdx.x;
+    life_sbb_state *st = states + k;
+    const int64_t it = st->iter;
+    const bool odd = (it & 1) != 0;
+    const int c0 = inst_chunk[k], c1 = inst_chunk[k + 1], r0 = inst_rank[k], r1 = inst_rank[k + 1];
+    const double r2 = block_sum_range(p_r, c0, c1);
+    const double vp2 = block_sum_range(p_vp, c0, c1);
+    const double gt2 = block_sumsq_range(gt, r0, r1);
+    const double vpp2 = odd ? 0.0 : block_sumsq_range(vpp, r0, r1);
+    if (threadIdx.x == 0) {
+        const double num = odd ? gt2 : vp2;
+        const double den = odd ? vp2 : vpp2;
+        st->alpha = den > 0.0 ? num / den : 0.0;
+        st->obj = 0.5 * r2;
+        st->gt_norm2 = gt2;
+        st->num = num;
+        st->den = den;
+        st->iter = it + 1;
+    }
+}
+
+// w <- [w - alpha_k g~]_+ with the step length of each rank's instance k.
+__global__ __launch_bounds__(kBlock) void k_update_batch(float *__restrict__ w_out, const float *__restrict__ w_rank,
+                                                          const float *__restrict__ gt,
+                                                          const int32_t *__restrict__ ext,
+                                                          const life_sbb_state *__restrict__ states,
+                                                          const int32_t *__restrict__ inst_rank, int n_inst, int nf)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nf) return;
+    int lo = 0, hi = n_inst;               // instance k with inst_rank[k] <= i < inst_rank[k+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (inst_rank[mid] <= i) lo = mid; else hi = mid;
+    }
+    const double x = (double)w_rank[i] - states[lo].alpha * (double)gt[i];
+    w_out[ext[i]] = x > 0.0 ? (float)x : 0.0f;
+}
+
 // w <- [w - alpha g~]_+  (eq. 5), evaluated in double and rounded once.  The
 // iterate and g~ are in fascicle-rank order; w_out is in the caller's order.
 __global__ __launch_bounds__(kBlock) void k_update(float *__restrict__ w_out, const float *__restrict__ w_rank,
@@ -871,6 +954,8 @@ struct life_plan_s {
     int32_t *chunk_vox = nullptr; // [n_chunks * kChunkVoxels]
     int32_t *chunk_map = nullptr; // [chunk_grid] chunk of each workgroup of the chunk kernels, -1 = none
     int chunk_grid = 0;
+    int schedule = life::kScheduleDefault;
+    std::vector<int64_t> chunk_work;   // host: padded entries per chunk (for re-scheduling)
     int32_t *wave_work = nullptr; // [n_chunks * n_tiles * kChunkWaves * kWorkInts]
     int16_t *atom_c = nullptr;    // [n_pad]
     int32_t *fas_c = nullptr;     // [n_pad]
@@ -897,6 +982,10 @@ struct life_plan_s {
     int32_t *a_ptr = nullptr;     // [Na + 1]
     int32_t *a_vox = nullptr, *a_fas = nullptr;   // [nnz] voxel, fascicle rank
     float *a_phi = nullptr;       // [nnz]
+    // instances of a batched plan (one for other plans): chunk and rank ranges
+    int n_inst = 1;
+    int32_t *inst_chunk = nullptr; // [n_inst + 1] first chunk of each instance
+    int32_t *inst_rank = nullptr;  // [n_inst + 1] first fascicle rank (= fascicle) of each instance
     // profiling
     bool profile = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -932,7 +1021,7 @@ void free_plan(life_plan_s *p)
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c, p->fas_c,
                     p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
                     p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
-                    p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi};
+                    p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -1146,9 +1235,13 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
     return life_plan_ex(dims, atom, voxel, fascicle, phi, nullptr, out);
 }
 
-extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
-                                    const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
-                                    life_plan_t *out)
+namespace {
+
+// Plan construction shared by life_plan, life_plan_ex and life_plan_batch
+// (n_inst <= 1: a single problem).
+life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
+                       const float *phi, const int16_t *voxel_xyz, int n_inst, const int32_t *vox_off,
+                       const int32_t *fas_off, life_plan_t *out)
 {
     if (!out) return LIFE_EINVAL;
     *out = nullptr;
@@ -1157,15 +1250,31 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     if ((st = life::validate_coords(dims, voxel_xyz)) != LIFE_OK) return st;
     const life_dims d = *dims;
     if (d.nnz > 0 && !phi) return LIFE_EINVAL;
+    const bool batched = n_inst > 1;
+    const int32_t one_v[2] = {0, d.n_voxels}, one_f[2] = {0, d.n_fascicles};
+    if (!batched) {
+        n_inst = 1;
+        vox_off = one_v;
+        fas_off = one_f;
+    }
     std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, ppos, pvox, vdsc;
     std::vector<int32_t> aptr, avox, afas, cmap;
+    std::vector<int64_t> chunk_work;
     std::vector<float> aphi;
     std::vector<int16_t> atom_v, atom_c;
     std::vector<int32_t> fas_v, fas_c;
     std::vector<float> phi_v, phi_c;
+    std::vector<int32_t> ichunk((size_t)n_inst + 1, 0);
     int64_t n_pad = 0;
     const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
-    const int n_chunks = tg.row_floats > 0 ? cdiv(d.n_voxels, kChunkVoxels) : 0;
+    if (batched) {
+        if (tg.row_floats == 0) return LIFE_EINVAL;   // batched plans need N_theta <= 128
+        if ((st = life::validate_indices(&d, atom, voxel, fascicle)) != LIFE_OK) return st;
+        if ((st = life::validate_instances(&d, n_inst, vox_off, fas_off, voxel, fascicle)) != LIFE_OK) return st;
+    }
+    const int32_t n_pos = life::padded_positions(&d, n_inst, vox_off);
+    if (n_pos < 0) return LIFE_ERANGE;
+    const int n_chunks = tg.row_floats > 0 ? cdiv(n_pos, kChunkVoxels) : 0;
     try {
         perm.resize((size_t)d.nnz);
         wperm.resize((size_t)d.nnz);
@@ -1174,10 +1283,24 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
         rank.resize((size_t)d.n_fascicles);
         ext.resize((size_t)d.n_fascicles);
         ppos.resize((size_t)d.n_voxels);
-        pvox.resize((size_t)d.n_voxels);
-        life::voxel_order(&d, voxel_xyz, ppos.data(), pvox.data());
-        st = life::plan_host(&d, atom, voxel, fascicle, voxel_xyz ? ppos.data() : nullptr, perm.data(), vptr.data(),
-                             rank.data(), wperm.data(), fptr.data());
+        pvox.resize((size_t)n_pos);
+        life::voxel_order(&d, voxel_xyz, n_inst, vox_off, ppos.data(), pvox.data());
+        std::vector<double> empty_key;
+        if (batched) {
+            // fascicles without nonzeros rank at the end of their own instance
+            empty_key.resize((size_t)d.n_fascicles);
+            int32_t base = 0;
+            for (int k = 0; k < n_inst; ++k) {
+                base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
+                ichunk[(size_t)k + 1] = base / kChunkVoxels;
+                for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_key[(size_t)f] = base;
+            }
+        } else {
+            ichunk[1] = n_chunks;
+        }
+        st = life::plan_host(&d, atom, voxel, fascicle, (voxel_xyz || batched) ? ppos.data() : nullptr, n_pos,
+                             batched ? empty_key.data() : nullptr, perm.data(), vptr.data(), rank.data(),
+                             wperm.data(), fptr.data());
         if (st != LIFE_OK) return st;
         for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
         atom_v.resize((size_t)d.nnz);
@@ -1210,7 +1333,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
         if (n_chunks > 0) {
             tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
             cvox.resize((size_t)n_chunks * kChunkVoxels);
-            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), pvox.data(), tptr.data(), cvox.data());
+            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), pvox.data(), n_pos, tptr.data(), cvox.data());
             n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), ppos.data(), atom_v.data(),
                                          fas_v.data(), phi_v.data(), vdsc.data(), wperm.data(), wwork, atom_c,
                                          fas_c, phi_c, zpos, wperm_z);
@@ -1222,6 +1345,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
                 work[(size_t)c] = end - wwork[(size_t)c * per_chunk];
             }
             cmap = life::chunk_schedule(work, life::kScheduleDefault);
+            chunk_work.swap(work);
         }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;
@@ -1239,6 +1363,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     p->n_chunks = n_chunks;
     p->n_pad = n_pad;
     p->chunk_grid = (int)cmap.size();
+    p->chunk_work.swap(chunk_work);
     const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
@@ -1289,6 +1414,9 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     chk(dalloc(&p->a_vox, (int64_t)avox.size()));
     chk(dalloc(&p->a_fas, (int64_t)afas.size()));
     chk(dalloc(&p->a_phi, (int64_t)aphi.size()));
+    p->n_inst = n_inst;
+    chk(dalloc(&p->inst_chunk, (int64_t)n_inst + 1));
+    chk(dalloc(&p->inst_rank, (int64_t)n_inst + 1));
     if (e == hipSuccess && n_chunks > 0) e = allow_lds();
     if (e != hipSuccess) {
         free_plan(p);
@@ -1317,6 +1445,8 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     up(p->a_vox, avox.data(), sizeof(int32_t) * avox.size());
     up(p->a_fas, afas.data(), sizeof(int32_t) * afas.size());
     up(p->a_phi, aphi.data(), sizeof(float) * aphi.size());
+    up(p->inst_chunk, ichunk.data(), sizeof(int32_t) * ichunk.size());
+    up(p->inst_rank, fas_off, sizeof(int32_t) * ((size_t)n_inst + 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_plan(p);
@@ -1324,6 +1454,24 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
     }
     *out = p;
     return LIFE_OK;
+}
+
+}  // namespace
+
+extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
+                                    const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                                    life_plan_t *out)
+{
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, 1, nullptr, nullptr, out);
+}
+
+extern "C" life_status life_plan_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                                       const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                                       const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                                       life_plan_t *out)
+{
+    if (n_inst < 1 || !vox_off || !fas_off) return LIFE_EINVAL;
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, out);
 }
 
 extern "C" life_status life_plan_destroy(life_plan_t plan)
@@ -1451,6 +1599,130 @@ life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float
 }
 
 }  // namespace
+
+namespace {
+
+// One SBB-NNLS iteration (Algorithm 1) of every instance of a batched plan.
+life_status enqueue_sbb_batch(life_plan_s *plan, const float *D, const float *b, float *w, life_sbb_state *states,
+                              hipStream_t s)
+{
+    const life_dims &d = plan->dims;
+    const int64_t ps = plan->part_stride;
+    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps;
+    const int nf = d.n_fascicles;
+    const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
+    life_status st;
+    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_MASK, s, [&] {
+            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
+        });
+        if (st != LIFE_OK) return st;
+    }
+    if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
+    // instances advance together: the first instance's parity gates the second WC
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, nullptr, Gate{states, 0}, s)) != LIFE_OK) return st;
+    st = launch(plan, LIFE_K_ALPHA, s, [&] {
+        k_alpha_batch<<<plan->n_inst, kAlphaThreads, 0, s>>>(p_r, p_vp, plan->inst_chunk, plan->gt, plan->vpp,
+                                                             plan->inst_rank, states);
+    });
+    if (st != LIFE_OK) return st;
+    if (nf > 0) {
+        st = launch(plan, LIFE_K_UPDATE, s, [&] {
+            k_update_batch<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, states,
+                                                               plan->inst_rank, plan->n_inst, nf);
+        });
+    }
+    return st;
+}
+
+}  // namespace
+
+extern "C" life_status life_plan_tune(life_plan_t plan, const float *D, const float *w, const float *y, int32_t reps,
+                                      int32_t *policy)
+{
+    if (!plan || reps < 1) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(w, d.n_fascicles) ||
+        !need(y, (int64_t)d.n_theta * d.n_voxels))
+        return LIFE_EINVAL;
+    if (!chunked(plan)) {
+        if (policy) *policy = plan->schedule;
+        return LIFE_OK;
+    }
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    const bool prof = plan->profile;
+    plan->profile = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
+    // install the schedule of policy pol (re-allocates the workgroup map)
+    auto install = [&](int pol) -> hipError_t {
+        const std::vector<int32_t> map = life::chunk_schedule(plan->chunk_work, (life::SchedulePolicy)pol);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        if (plan->chunk_map) (void)hipFree(plan->chunk_map);
+        plan->chunk_map = nullptr;
+        if ((e = dalloc(&plan->chunk_map, (int64_t)map.size())) != hipSuccess) return e;
+        e = hipMemcpy(plan->chunk_map, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice);
+        plan->chunk_grid = (int)map.size();
+        plan->schedule = pol;
+        return e;
+    };
+    const int pols[] = {life::kScheduleIndex, life::kScheduleXcdCount, life::kScheduleXcdWork};
+    float best = 0.f;
+    int best_pol = plan->schedule;
+    life_status st = LIFE_OK;
+    for (int pol : pols) {
+        if (install(pol) != hipSuccess) { st = LIFE_EDEVICE; break; }
+        auto run = [&]() {
+            if (enqueue_gather(plan, w, nullptr) != LIFE_OK) return false;
+            if (enqueue_dsc(plan, D, plan->w_rank, nullptr, plan->r, nullptr, nullptr) != LIFE_OK) return false;
+            return enqueue_wc(plan, D, y, plan->g, nullptr, nullptr, Gate{nullptr, 0}, nullptr) == LIFE_OK;
+        };
+        if (!run()) { st = LIFE_EDEVICE; break; }                 // warm-up
+        float ms = 0.f;
+        bool ok = hipEventRecord(e0, nullptr) == hipSuccess;
+        for (int i = 0; ok && i < reps; ++i) ok = run();
+        ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok) { st = LIFE_EDEVICE; break; }
+        if (best_pol < 0 || pol == pols[0] || ms < best) {
+            best = ms;
+            best_pol = pol;
+        }
+    }
+    if (st == LIFE_OK && install(best_pol) != hipSuccess) st = LIFE_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->profile = prof;
+    if (st == LIFE_OK && policy) *policy = best_pol;
+    return st;
+}
+
+extern "C" life_status life_plan_instances(life_plan_t plan, int32_t *n_inst)
+{
+    if (!plan || !n_inst) return LIFE_EINVAL;
+    *n_inst = plan->n_inst;
+    return LIFE_OK;
+}
+
+extern "C" life_status life_sbbnnls_step_batch(life_plan_t plan, const float *D, const float *b, float *w,
+                                               life_sbb_state *states, void *stream)
+{
+    if (!plan || !states) return LIFE_EINVAL;
+    const life_dims &d = plan->dims;
+    if (!chunked(plan) && plan->n_inst > 1) return LIFE_EINVAL;
+    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(b, (int64_t)d.n_theta * d.n_voxels) ||
+        !need(w, d.n_fascicles))
+        return LIFE_EINVAL;
+    if (!chunked(plan)) return life_sbbnnls_step(plan, D, b, w, states, stream);   // one instance
+    DeviceGuard gd(plan->device);
+    if (!gd.ok) return LIFE_EDEVICE;
+    return enqueue_sbb_batch(plan, D, b, w, states, static_cast<hipStream_t>(stream));
+}
 
 extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
                                          life_sbb_state *state, void *stream)

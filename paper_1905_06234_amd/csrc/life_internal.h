@@ -15,15 +15,32 @@ life_status validate_indices(const life_dims *d, const int16_t *atom, const int3
                              const int32_t *fascicle);
 life_status validate_coords(const life_dims *d, const int16_t *voxel_xyz);
 
-// Voxel processing order: voxel id order, or, given grid coordinates, the Morton
-// (Z-order) sequence of the coordinates (ties by id), so that consecutive voxels
-// form compact blocks.  proc_pos[v] = position of voxel v; proc_vox[k] = voxel at k.
-void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int32_t *proc_pos, int32_t *proc_vox);
+// Batched plans: n_inst independent problems sharing D, concatenated into one
+// block-diagonal problem; instance k owns voxels [vox_off[k], vox_off[k+1]) and
+// fascicles [fas_off[k], fas_off[k+1]), and each nonzero lies in one instance.
+life_status validate_instances(const life_dims *d, int n_inst, const int32_t *vox_off, const int32_t *fas_off,
+                               const int32_t *voxel, const int32_t *fascicle);
 
-// Host restructuring (see life_plan_host in life.h); proc_pos may be NULL (id order).
+// Number of voxel processing positions: n_voxels for one instance; with several,
+// each instance's block is padded to whole chunks so no chunk spans two
+// instances.  -1 if it exceeds the 32-bit limit.
+int32_t padded_positions(const life_dims *d, int n_inst, const int32_t *vox_off);
+
+// Voxel processing order: instance by instance (n_inst <= 1: one instance, no
+// padding); inside an instance voxel id order, or, given grid coordinates, the
+// Morton (Z-order) sequence of the coordinates (ties by id), so that consecutive
+// voxels form compact blocks.  proc_pos[v] = position of voxel v; proc_vox[k] =
+// voxel at position k, -1 for padding (padded_positions entries).
+void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int n_inst, const int32_t *vox_off,
+                 int32_t *proc_pos, int32_t *proc_vox);
+
+// Host restructuring (see life_plan_host in life.h); proc_pos may be NULL (id
+// order); n_pos = number of processing positions; empty_key (NULL = after all
+// others) gives the ranking key of fascicles without nonzeros (batched plans rank
+// them at the end of their own instance).
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
-                      const int32_t *proc_pos, int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank,
-                      int32_t *wc_perm, int32_t *fas_ptr);
+                      const int32_t *proc_pos, int32_t n_pos, const double *empty_key, int32_t *dsc_perm,
+                      int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
 
 // Work decomposition of the chunked (LDS-tiled) kernels, computed on the host.
 //   The dictionary is staged in shared memory one atom tile at a time: n_tiles
@@ -55,9 +72,10 @@ TileGeom tile_geometry(int n_theta, int n_atoms);
 // tile_ptr[v*(n_tiles+1) + t]: first DSC position of voxel v whose atom is >= t*tile_atoms
 // (the segment's atoms are ascending); tile_ptr[v*(n_tiles+1) + n_tiles] = end of segment.
 // chunk_vox[c*kChunkVoxels + wave*kWaveVoxels + j]: voxel owned by slot j of a wave in chunk c
-// (-1 = empty), balanced inside each chunk by longest-processing-time assignment.
+// (-1 = empty), balanced inside each chunk by longest-processing-time assignment;
+// chunk c holds processing positions [64c, 64c + 64) of n_pos.
 void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                const int32_t *proc_vox, int32_t *tile_ptr, int32_t *chunk_vox);
+                const int32_t *proc_vox, int32_t n_pos, int32_t *tile_ptr, int32_t *chunk_vox);
 
 // Chunked layout: for every (chunk c, tile t, wave w) one contiguous range of the
 // padded arrays holds the tile-t sub-ranges of the wave's voxel slots j = 0..3,

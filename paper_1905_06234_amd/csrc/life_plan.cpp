@@ -92,7 +92,7 @@ uint64_t morton_key(const int16_t *c)
 // Fascicle rank: fascicles in order of the mean processing position of their
 // voxels (empty fascicles last, ties by index).
 void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fascicle, const int32_t *proc_pos,
-                    int32_t *rank)
+                    const double *empty_key, int32_t *rank)
 {
     const int32_t nf = d->n_fascicles;
     std::vector<double> sum(static_cast<size_t>(nf), 0.0);
@@ -102,7 +102,8 @@ void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fas
         ++cnt[fascicle[c]];
     }
     std::vector<double> key(static_cast<size_t>(nf));
-    for (int32_t f = 0; f < nf; ++f) key[f] = cnt[f] ? sum[f] / static_cast<double>(cnt[f]) : 1e300;
+    for (int32_t f = 0; f < nf; ++f)
+        key[f] = cnt[f] ? sum[f] / static_cast<double>(cnt[f]) : (empty_key ? empty_key[f] : 1e300);
     std::vector<int32_t> order(static_cast<size_t>(nf));
     for (int32_t f = 0; f < nf; ++f) order[f] = f;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
@@ -111,27 +112,65 @@ void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fas
 
 }  // namespace
 
-void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int32_t *proc_pos, int32_t *proc_vox)
+life_status validate_instances(const life_dims *d, int n_inst, const int32_t *vox_off, const int32_t *fas_off,
+                               const int32_t *voxel, const int32_t *fascicle)
+{
+    if (n_inst < 1 || !vox_off || !fas_off) return LIFE_EINVAL;
+    if (vox_off[0] != 0 || fas_off[0] != 0 || vox_off[n_inst] != d->n_voxels || fas_off[n_inst] != d->n_fascicles)
+        return LIFE_EINVAL;
+    for (int k = 0; k < n_inst; ++k)
+        if (vox_off[k + 1] < vox_off[k] || fas_off[k + 1] < fas_off[k]) return LIFE_EINVAL;
+    // every nonzero's voxel and fascicle lie in one instance (block-diagonal M)
+    std::vector<int32_t> fas_inst(static_cast<size_t>(d->n_fascicles));
+    for (int k = 0; k < n_inst; ++k)
+        for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) fas_inst[f] = k;
+    for (int64_t c = 0; c < d->nnz; ++c) {
+        const int k = fas_inst[fascicle[c]];
+        if (voxel[c] < vox_off[k] || voxel[c] >= vox_off[k + 1]) return LIFE_ERANGE;
+    }
+    return LIFE_OK;
+}
+
+int32_t padded_positions(const life_dims *d, int n_inst, const int32_t *vox_off)
+{
+    if (n_inst <= 1) return d->n_voxels;
+    int64_t n = 0;
+    for (int k = 0; k < n_inst; ++k) n += (vox_off[k + 1] - vox_off[k] + kChunkVoxels - 1) / kChunkVoxels * kChunkVoxels;
+    return n > kMaxNnz ? -1 : static_cast<int32_t>(n);
+}
+
+void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int n_inst, const int32_t *vox_off,
+                 int32_t *proc_pos, int32_t *proc_vox)
 {
     const int32_t nv = d->n_voxels;
-    std::vector<int32_t> order(static_cast<size_t>(nv));
-    for (int32_t v = 0; v < nv; ++v) order[v] = v;
-    if (voxel_xyz) {
-        std::vector<uint64_t> key(static_cast<size_t>(nv));
-        for (int32_t v = 0; v < nv; ++v) {
-            key[v] = morton_key(voxel_xyz + 3 * (int64_t)v);
+    const int32_t one[2] = {0, nv};
+    if (n_inst <= 1) vox_off = one;
+    const int ni = n_inst <= 1 ? 1 : n_inst;
+    int32_t base = 0;
+    std::vector<int32_t> order;
+    std::vector<uint64_t> key;
+    for (int k = 0; k < ni; ++k) {
+        const int32_t v0 = vox_off[k], v1 = vox_off[k + 1], n = v1 - v0;
+        order.resize(static_cast<size_t>(n));
+        for (int32_t i = 0; i < n; ++i) order[i] = v0 + i;
+        if (voxel_xyz) {
+            key.resize(static_cast<size_t>(n));
+            for (int32_t i = 0; i < n; ++i) key[i] = morton_key(voxel_xyz + 3 * (int64_t)(v0 + i));
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b) { return key[a - v0] < key[b - v0]; });
         }
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-    }
-    for (int32_t k = 0; k < nv; ++k) {
-        if (proc_vox) proc_vox[k] = order[k];
-        if (proc_pos) proc_pos[order[k]] = k;
+        const int32_t span = ni == 1 ? n : (n + kChunkVoxels - 1) / kChunkVoxels * kChunkVoxels;
+        for (int32_t i = 0; i < span; ++i) {
+            if (proc_vox) proc_vox[base + i] = i < n ? order[i] : -1;
+            if (proc_pos && i < n) proc_pos[order[i]] = base + i;
+        }
+        base += span;
     }
 }
 
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
-                      const int32_t *proc_pos, int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank,
-                      int32_t *wc_perm, int32_t *fas_ptr)
+                      const int32_t *proc_pos, int32_t n_pos, const double *empty_key, int32_t *dsc_perm,
+                      int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
 {
     life_status st = validate_dims(d);
     if (st != LIFE_OK) return st;
@@ -153,7 +192,7 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
             segment_offsets(keys.data(), n, d->n_voxels, vox_ptr);
         }
         std::vector<int32_t> rank(static_cast<size_t>(d->n_fascicles));
-        fascicle_ranks(d, voxel, fascicle, proc_pos, rank.data());
+        fascicle_ranks(d, voxel, fascicle, proc_pos, empty_key, rank.data());
         if (fas_rank && d->n_fascicles)
             std::memcpy(fas_rank, rank.data(), sizeof(int32_t) * static_cast<size_t>(d->n_fascicles));
         if (wc_perm || fas_ptr) {
@@ -162,8 +201,8 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
             std::vector<int32_t> w(static_cast<size_t>(n));
             for (int64_t p = 0; p < n; ++p) a[p] = static_cast<int32_t>(p);
             if (proc_pos) {
-                counting_sort(a.data(), w.data(), n, d->n_voxels, [&](int32_t p) { return proc_pos[voxel[b[p]]]; },
-                              cnt);
+                counting_sort(a.data(), w.data(), n, std::max(n_pos, d->n_voxels),
+                              [&](int32_t p) { return proc_pos[voxel[b[p]]]; }, cnt);
                 std::swap(a, w);
             }
             counting_sort(a.data(), w.data(), n, d->n_fascicles, [&](int32_t p) { return rank[fascicle[b[p]]]; },
@@ -196,7 +235,7 @@ TileGeom tile_geometry(int n_theta, int n_atoms)
 }
 
 void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                const int32_t *proc_vox, int32_t *tile_ptr, int32_t *chunk_vox)
+                const int32_t *proc_vox, int32_t n_pos, int32_t *tile_ptr, int32_t *chunk_vox)
 {
     const int nv = d->n_voxels, T = tg.n_tiles;
     for (int v = 0; v < nv; ++v) {
@@ -209,12 +248,15 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
         }
         tile_ptr[(int64_t)v * (T + 1) + T] = end;
     }
-    const int nchunks = (nv + kChunkVoxels - 1) / kChunkVoxels;
+    const int nchunks = (n_pos + kChunkVoxels - 1) / kChunkVoxels;
     std::vector<int> ids;
     for (int c = 0; c < nchunks; ++c) {
-        const int k0 = c * kChunkVoxels, k1 = std::min(nv, k0 + kChunkVoxels);
+        const int k0 = c * kChunkVoxels, k1 = std::min(n_pos, k0 + kChunkVoxels);
         ids.clear();
-        for (int k = k0; k < k1; ++k) ids.push_back(proc_vox ? proc_vox[k] : k);
+        for (int k = k0; k < k1; ++k) {
+            const int v = proc_vox ? proc_vox[k] : k;
+            if (v >= 0) ids.push_back(v);
+        }
         // longest first; ties keep processing order so the plan is unique
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
             return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
@@ -367,9 +409,40 @@ extern "C" life_status life_plan_host(const life_dims *dims, const int16_t *atom
         std::vector<int32_t> pos;
         if (voxel_xyz) {
             pos.resize((size_t)dims->n_voxels);
-            life::voxel_order(dims, voxel_xyz, pos.data(), nullptr);
+            life::voxel_order(dims, voxel_xyz, 1, nullptr, pos.data(), nullptr);
         }
-        return life::plan_host(dims, atom, voxel, fascicle, voxel_xyz ? pos.data() : nullptr, dsc_perm, vox_ptr,
+        return life::plan_host(dims, atom, voxel, fascicle, voxel_xyz ? pos.data() : nullptr, dims->n_voxels, nullptr,
+                               dsc_perm, vox_ptr, fas_rank, wc_perm, fas_ptr);
+    } catch (const std::bad_alloc &) {
+        return LIFE_ENOMEM;
+    }
+}
+
+extern "C" life_status life_plan_host_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                                            const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                                            const int32_t *fascicle, const int16_t *voxel_xyz, int32_t *proc_pos,
+                                            int32_t *dsc_perm, int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm,
+                                            int32_t *fas_ptr)
+{
+    life_status st = life::validate_dims(dims);
+    if (st != LIFE_OK) return st;
+    if ((st = life::validate_coords(dims, voxel_xyz)) != LIFE_OK) return st;
+    if ((st = life::validate_indices(dims, atom, voxel, fascicle)) != LIFE_OK) return st;
+    if ((st = life::validate_instances(dims, n_inst, vox_off, fas_off, voxel, fascicle)) != LIFE_OK) return st;
+    try {
+        const int32_t n_pos = life::padded_positions(dims, n_inst, vox_off);
+        if (n_pos < 0) return LIFE_ERANGE;
+        std::vector<int32_t> pos((size_t)dims->n_voxels);
+        life::voxel_order(dims, voxel_xyz, n_inst, vox_off, pos.data(), nullptr);
+        std::vector<double> empty_key((size_t)dims->n_fascicles);
+        int64_t base = 0;
+        for (int k = 0; k < n_inst; ++k) {
+            const int32_t nvk = vox_off[k + 1] - vox_off[k];
+            base += n_inst > 1 ? (nvk + life::kChunkVoxels - 1) / life::kChunkVoxels * life::kChunkVoxels : nvk;
+            for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_key[(size_t)f] = (double)base;
+        }
+        if (proc_pos && dims->n_voxels) std::memcpy(proc_pos, pos.data(), sizeof(int32_t) * pos.size());
+        return life::plan_host(dims, atom, voxel, fascicle, pos.data(), n_pos, empty_key.data(), dsc_perm, vox_ptr,
                                fas_rank, wc_perm, fas_ptr);
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;

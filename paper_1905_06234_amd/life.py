@@ -48,6 +48,13 @@ _SIGS = {
     "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "life_plan": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "life_plan_ex": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "life_plan_batch": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                       ctypes.POINTER(_P)]),
+    "life_plan_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "life_plan_host_batch": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                            _P, _P, _P, _P]),
+    "life_plan_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "life_sbbnnls_step_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "life_plan_destroy": (ctypes.c_int, [_P]),
     "life_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(Dims)]),
     "life_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
@@ -120,6 +127,47 @@ def plan_host(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom,
     return out
 
 
+def concat_instances(instances, morton: bool = True):
+    """Union COO of problems sharing a dictionary: (dims, vox_off, fas_off, atom,
+    voxel, fascicle, phi, voxel_xyz or None), instances concatenated in order."""
+    inst = list(instances)
+    if not inst:
+        raise ValueError("no instances")
+    nt, na = inst[0].n_theta, inst[0].n_atoms
+    if any(c.n_theta != nt or c.n_atoms != na for c in inst):
+        raise ValueError("instances must share the dictionary shape")
+    vox_off = np.zeros(len(inst) + 1, np.int32)
+    fas_off = np.zeros(len(inst) + 1, np.int32)
+    vox_off[1:] = np.cumsum([c.n_voxels for c in inst])
+    fas_off[1:] = np.cumsum([c.n_fascicles for c in inst])
+    atom = np.concatenate([np.asarray(c.atom, np.int16) for c in inst])
+    voxel = np.concatenate([np.asarray(c.voxel, np.int64) + vox_off[k] for k, c in enumerate(inst)])
+    fascicle = np.concatenate([np.asarray(c.fascicle, np.int64) + fas_off[k] for k, c in enumerate(inst)])
+    phi = np.ascontiguousarray(np.concatenate([np.asarray(c.phi, np.float32) for c in inst]))
+    atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+    xyz = None
+    if morton:
+        xyz = _xyz(np.concatenate([np.asarray(c.voxel_xyz, np.int16) for c in inst]), int(vox_off[-1]))
+    dims = Dims(nt, na, int(vox_off[-1]), int(fas_off[-1]), atom.shape[0])
+    return dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz
+
+
+def plan_host_batch(instances, morton: bool = True, raw=None) -> Dict[str, np.ndarray]:
+    """Host-only restructuring of a batched plan (life_plan_host_batch).  raw: an
+    already concatenated tuple from concat_instances (to test rejected inputs)."""
+    dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = raw or concat_instances(instances, morton)
+    nnz, nv, nf = dims.nnz, dims.n_voxels, dims.n_fascicles
+    out = {"proc_pos": np.empty(max(nv, 0), np.int32), "dsc_perm": np.empty(nnz, np.int32),
+           "vox_ptr": np.empty(nv + 1, np.int32), "fas_rank": np.empty(nf, np.int32),
+           "wc_perm": np.empty(nnz, np.int32), "fas_ptr": np.empty(nf + 1, np.int32)}
+    _check("life_plan_host_batch", load().life_plan_host_batch(
+        ctypes.byref(dims), len(vox_off) - 1, _np_ptr(vox_off), _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
+        _np_ptr(fascicle), _np_ptr(xyz), *(_np_ptr(out[k]) for k in ("proc_pos", "dsc_perm", "vox_ptr", "fas_rank",
+                                                                      "wc_perm", "fas_ptr"))))
+    out.update({"vox_off": vox_off, "fas_off": fas_off})
+    return out
+
+
 def _torch():
     import torch
     return torch
@@ -141,20 +189,22 @@ def _stream(stream, device):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def new_state(device=None, iteration: int = 0):
-    """A zeroed life_sbb_state on the device (as 6 float64 slots; slot 0 is int64 iter)."""
+def new_state(device=None, iteration: int = 0, n: Optional[int] = None):
+    """A zeroed life_sbb_state on the device (as 6 float64 slots; slot 0 is int64
+    iter); n given: a contiguous array of n states (batched plans)."""
     torch = _torch()
-    st = torch.zeros(6, dtype=torch.float64, device=device or "cuda")
+    st = torch.zeros((n if n is not None else 1) * 6, dtype=torch.float64, device=device or "cuda")
     if iteration:
-        st.view(torch.int64)[0] = iteration
+        st.view(-1, 6).view(torch.int64)[:, 0] = iteration
     return st
 
 
-def read_state(state) -> Dict[str, float]:
+def read_state(state, k: Optional[int] = None) -> Dict[str, float]:
+    """Fields of a state (k given: of state k of an array of states)."""
     torch = _torch()
-    host = state.detach().cpu()
+    host = state.detach().cpu().view(-1, 6)[0 if k is None else k]
     vals = host.numpy()
-    out = {k: float(vals[i]) for i, k in enumerate(STATE_FIELDS)}
+    out = {kk: float(vals[i]) for i, kk in enumerate(STATE_FIELDS)}
     out["iter"] = int(host.view(torch.int64)[0])
     return out
 
@@ -182,6 +232,53 @@ class Plan:
                                                     _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz),
                                                     ctypes.byref(self._h)))
         self.device = _torch().cuda.current_device()
+
+    @classmethod
+    def batch(cls, instances, morton: bool = True) -> "Plan":
+        """A batched plan (life_plan_batch) of problems sharing one dictionary.
+
+        instances: objects with n_theta, n_atoms, n_voxels, n_fascicles, atom,
+        voxel, fascicle, phi (and voxel_xyz when morton).  The union concatenates
+        them in order; ``vox_off`` / ``fas_off`` give each instance's slice of the
+        union's signal and weight vectors."""
+        dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = concat_instances(instances, morton)
+        n_inst = len(vox_off) - 1
+        self = cls.__new__(cls)
+        self.dims = dims
+        self._h = ctypes.c_void_p()
+        _check("life_plan_batch", load().life_plan_batch(ctypes.byref(self.dims), n_inst, _np_ptr(vox_off),
+                                                         _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
+                                                         _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz),
+                                                         ctypes.byref(self._h)))
+        self.device = _torch().cuda.current_device()
+        self.vox_off, self.fas_off = vox_off, fas_off
+        return self
+
+    @property
+    def n_inst(self) -> int:
+        n = ctypes.c_int32()
+        _check("life_plan_instances", load().life_plan_instances(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def tune(self, D, w, y, reps: int = 3) -> int:
+        """Keep the fastest work schedule for this plan (life_plan_tune); returns it."""
+        pol = ctypes.c_int32()
+        _check("life_plan_tune", load().life_plan_tune(self._h, self._d(D), _dev_f32(w, self.dims.n_fascicles, "w"),
+                                                       _dev_f32(y, self.n_signal, "y"), int(reps),
+                                                       ctypes.byref(pol)))
+        return int(pol.value)
+
+    def sbbnnls_step_batch(self, D, b, w, states, stream=None):
+        """One SBB-NNLS iteration of every instance; states from new_state(device, n=n_inst)."""
+        torch = _torch()
+        if not (isinstance(states, torch.Tensor) and states.is_cuda and states.is_contiguous()
+                and states.numel() * states.element_size() == 48 * self.n_inst):
+            raise ValueError("states must be a contiguous device tensor of n_inst 48-byte states (see new_state)")
+        _check("life_sbbnnls_step_batch",
+               load().life_sbbnnls_step_batch(self._h, self._d(D), _dev_f32(b, self.n_signal, "b"),
+                                              _dev_f32(w, self.dims.n_fascicles, "w"),
+                                              ctypes.c_void_p(states.data_ptr()), _stream(stream, w.device)))
+        return w
 
     @classmethod
     def from_connectome(cls, c, morton: bool = True) -> "Plan":

@@ -60,6 +60,7 @@ class Config:
     density_smooth: float          # Gaussian smoothing (voxels) of the density field
     bval: float
     seed: int
+    dict_seed: Optional[int] = None   # seed of the gradient directions (None = seed)
 
 
 CONFIGS: Dict[str, Config] = {
@@ -299,8 +300,12 @@ def _make(name: str, n_fascicles: Optional[int]) -> Connectome:
     cfg = CONFIGS[name]
     if n_fascicles is not None:
         cfg = dataclasses.replace(cfg, n_fascicles=int(n_fascicles))
-    seed = cfg.seed
-    g = _unit(_rng(seed, _S_GRAD), cfg.n_theta)
+    return _make_cfg(cfg)
+
+
+def _make_cfg(cfg: Config) -> Connectome:
+    name, seed = cfg.name, cfg.seed
+    g = _unit(_rng(cfg.dict_seed if cfg.dict_seed is not None else seed, _S_GRAD), cfg.n_theta)
     if cfg.atoms == "fibonacci":
         u = fibonacci_sphere(cfg.n_atoms)
     else:
@@ -340,6 +345,28 @@ def _make(name: str, n_fascicles: Optional[int]) -> Connectome:
         noise=_rng(seed, _S_NOISE).standard_normal(cfg.n_theta * nv).astype(np.float32),
         grid=cfg.grid, voxel_xyz=voxel_xyz,
     )
+
+
+def make_batch(n_inst: int = 32, seed: int = 7, scale: float = 1.0,
+               nv_range: Tuple[int, int] = (30_000, 150_000), nf_range: Tuple[int, int] = (20_000, 400_000),
+               steps: Tuple[int, int] = (20, 120)) -> list:
+    """Uneven instances that share one dictionary (the mid configuration's: 96
+    directions, 1057 Fibonacci atoms).  Instance k has an ellipsoidal mask of
+    about U(nv_range)*scale voxels and log-uniform(nf_range)*scale fascicles of
+    uniform(steps) walk steps; each instance has its own seeds."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 99]))
+    base = CONFIGS["mid"]
+    out = []
+    for k in range(n_inst):
+        nv = max(64, int(rng.uniform(*nv_range) * scale))
+        nf = max(16, int(np.exp(rng.uniform(np.log(nf_range[0]), np.log(nf_range[1]))) * scale))
+        r = (nv / (4.0 / 3.0 * math.pi * 0.95 * 0.9)) ** (1.0 / 3.0)
+        n = int(math.ceil(2 * r + 2))
+        cfg = dataclasses.replace(base, name=f"batch{seed}_{k}", grid=(n, n, n),
+                                  semi_axes=(r, 0.95 * r, 0.9 * r), n_fascicles=nf, steps=steps,
+                                  seed=1000 * seed + k, dict_seed=base.seed)
+        out.append(_make_cfg(cfg))
+    return out
 
 
 def random_coo(n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, nnz: int,

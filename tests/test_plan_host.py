@@ -122,3 +122,78 @@ def test_null_arguments_rejected():
     assert lib.life_wc(None, None, None, None, None) == 1
     assert lib.life_sbbnnls_step(None, None, None, None, None, None) == 1
     assert lib.life_plan_destroy(None) == 0
+
+
+# ----------------------------------------------------------------------------- batched plans
+
+
+def _batch_instances():
+    b = synth.make_batch(3, seed=5, scale=0.02)
+    # an instance with extra fascicles that cross no voxel (empty fascicles) and a random one
+    r = synth.random_coo(96, 1057, 300, 80, 900, seed=11)
+    r = synth.Connectome(name="r", n_theta=r.n_theta, n_atoms=r.n_atoms, n_voxels=r.n_voxels,
+                         n_fascicles=r.n_fascicles + 5, atom=r.atom, voxel=r.voxel, fascicle=r.fascicle,
+                         phi=r.phi, D=b[0].D, w0=np.zeros(r.n_fascicles + 5, np.float32),
+                         w_true=np.zeros(r.n_fascicles + 5, np.float32), noise=r.noise, grid=r.grid,
+                         voxel_xyz=np.random.default_rng(3).integers(0, 9, (r.n_voxels, 3)).astype(np.int16))
+    return b[:2] + [r] + b[2:]
+
+
+def _reference_batch_plan(inst):
+    """Batched restructuring computed independently: positions instance by instance
+    (Morton inside, blocks padded to 64), ranks by mean position (empty fascicles at
+    the end of their instance), then the same lexsorts as reference_plan."""
+    from conftest import morton_positions
+    dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = life.concat_instances(inst)
+    pp = np.empty(dims.n_voxels, np.int64)
+    empty_key = np.empty(dims.n_fascicles)
+    base = 0
+    for k in range(len(inst)):
+        v0, v1 = vox_off[k], vox_off[k + 1]
+        pp[v0:v1] = base + morton_positions(xyz[v0:v1])
+        base += -(-(v1 - v0) // 64) * 64
+        empty_key[fas_off[k]:fas_off[k + 1]] = base
+    pos = np.arange(dims.nnz)
+    cnt = np.bincount(fascicle, minlength=dims.n_fascicles)
+    tot = np.bincount(fascicle, weights=pp[voxel].astype(np.float64), minlength=dims.n_fascicles)
+    key = np.where(cnt > 0, tot / np.maximum(cnt, 1), empty_key)
+    order = np.argsort(key, kind="stable")
+    rank = np.empty(dims.n_fascicles, np.int64)
+    rank[order] = np.arange(dims.n_fascicles)
+    dsc = np.lexsort((pos, fascicle, atom, voxel))
+    wc_in = np.lexsort((pos, atom, pp[voxel], rank[fascicle]))
+    inv = np.empty(dims.nnz, np.int64)
+    inv[dsc] = pos
+    return {"proc_pos": pp, "dsc_perm": dsc,
+            "vox_ptr": np.searchsorted(voxel[dsc], np.arange(dims.n_voxels + 1)),
+            "fas_rank": rank, "wc_perm": inv[wc_in],
+            "fas_ptr": np.searchsorted(rank[fascicle[wc_in]], np.arange(dims.n_fascicles + 1))}
+
+
+def test_batch_host_plan_bit_exact():
+    inst = _batch_instances()
+    p = life.plan_host_batch(inst)
+    ref = _reference_batch_plan(inst)
+    for k in ("proc_pos", "dsc_perm", "vox_ptr", "fas_rank", "wc_perm", "fas_ptr"):
+        assert np.array_equal(p[k], ref[k]), k
+    # every instance's fascicles take one contiguous block of ranks, in instance order
+    fo = p["fas_off"]
+    for k in range(len(inst)):
+        assert np.array_equal(np.sort(p["fas_rank"][fo[k]:fo[k + 1]]), np.arange(fo[k], fo[k + 1]))
+
+
+def test_batch_rejects_nonzero_across_instances():
+    inst = _batch_instances()
+    raw = list(life.concat_instances(inst))
+    voxel = raw[4].copy()
+    voxel[0] = raw[1][-1] - 1                   # first nonzero (instance 0) moved into the last instance
+    raw[4] = voxel
+    with pytest.raises(life.LifeError) as e:
+        life.plan_host_batch(None, raw=tuple(raw))
+    assert e.value.status == 2
+    bad = list(life.concat_instances(inst))
+    bad[1] = bad[1].copy()
+    bad[1][1] = bad[1][2] + 1                   # offsets must not decrease
+    with pytest.raises(life.LifeError) as e:
+        life.plan_host_batch(None, raw=tuple(bad))
+    assert e.value.status == 1
