@@ -197,6 +197,149 @@ def cpu_baseline(c, target_s: float):
                       f"one DSC ({t_dsc:.2f} s) + one WC ({t_wc:.2f} s), sequential C, float64"}
 
 
+def _time_ms(fn, reps: int) -> float:
+    """Wall milliseconds per call of fn (device-synchronized bracket)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def bench_adam(args):
+    """Joint (w, D) Adam on ||y_obs - M(D) w||^2 through the library's
+    differentiable DSC (forward DSC; backward WC + dictionary gradient), timed
+    against plain DSC+WC pairs on the same plan (mid synthetic connectome)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_06234_amd import autograd, life
+
+    life.load()
+    dev = torch.device("cuda:0")
+    c = synth.make("mid")
+    plan = life.Plan.from_connectome(c)
+    log(f"adam: mid nnz={c.nnz}, plan built")
+    D0 = torch.from_numpy(c.D).to(dev)
+    w0 = torch.from_numpy(c.w0).to(dev)
+    y_obs = plan.dsc(D0, torch.from_numpy(c.w_true).to(dev))
+    y_obs += 0.05 * torch.sqrt(torch.mean(y_obs.double() ** 2)).float() * torch.from_numpy(c.noise).to(dev)
+    D = D0.clone().requires_grad_(True)
+    w = w0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([D, w], lr=1e-3)
+
+    def adam_step():
+        opt.zero_grad(set_to_none=False)
+        L = autograd.loss(plan, D, w, y_obs)
+        L.backward()
+        opt.step()
+        with torch.no_grad():
+            w.clamp_(min=0.0)
+        return L
+
+    y = torch.empty(plan.n_signal, device=dev)
+    g = torch.empty(plan.dims.n_fascicles, device=dev)
+
+    def pair():
+        plan.dsc(D0, w0, y)
+        plan.wc(D0, y_obs, g)
+
+    for _ in range(args.warmup):
+        adam_step()
+        pair()
+    L0 = float(autograd.loss(plan, D, w, y_obs))
+    plan.profile_read()
+    plan.profile_enable(True)
+    t_adam = _time_ms(adam_step, args.adam_steps)
+    plan.profile_enable(False)
+    ms, cnt = plan.profile_read()
+    L1 = float(autograd.loss(plan, D, w, y_obs))
+    t_pair = _time_ms(pair, args.steps)
+    avg = {k: round(ms[k] / cnt[k], 4) for k in ms if cnt[k]}
+    out = {"metric": "joint (w, D) Adam step on ||y_obs - M(D)w||^2 / plain DSC+WC pair time",
+           "value": round(t_adam / t_pair, 4), "unit": "ratio", "higher_is_better": False, "n_gpus": 1,
+           "steps": args.adam_steps, "warmup": args.warmup, "ms_per_adam_step": round(t_adam, 4),
+           "ms_per_dsc_wc_pair": round(t_pair, 4), "dtype": "f32", "data": "synthetic",
+           "loss_before": L0, "loss_after": L1, "kernel_avg_ms": avg,
+           "config": {"workload": "mid synthetic connectome, dictionary learning", "n_theta": c.n_theta,
+                      "n_atoms": c.n_atoms, "n_voxels": c.n_voxels, "n_fascicles": c.n_fascicles, "nnz": c.nnz}}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """32 uneven instances sharing one dictionary: one batched SBB-NNLS iteration
+    over all of them (eager, and replayed from a hipGraph) against the 32
+    single-instance plans stepped one after another."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_06234_amd import life
+
+    life.load()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    inst = synth.make_batch(args.instances, seed=7, scale=args.batch_scale)
+    nnz = sum(c.nnz for c in inst)
+    log(f"batched: {len(inst)} instances, nnz {nnz} ({time.perf_counter() - t0:.0f} s)")
+    bp = life.Plan.batch(inst)
+    singles = [life.Plan.from_connectome(c) for c in inst]
+    log("plans built")
+    D = torch.from_numpy(inst[0].D.ravel()).to(dev)
+    bs, ws = [], []
+    for c, sp in zip(inst, singles):
+        y = sp.dsc(D, torch.from_numpy(c.w_true).to(dev))
+        bs.append(y + 0.05 * torch.sqrt(torch.mean(y.double() ** 2)).float() * torch.from_numpy(c.noise).to(dev))
+        ws.append(torch.from_numpy(c.w0).to(dev))
+    b_all = torch.cat(bs)
+    w_all = torch.cat(ws)
+    states = life.new_state(dev, n=len(inst))
+    policy = bp.tune(D, w_all, b_all, reps=3)
+    log(f"tuned schedule {policy}")
+
+    def batched():
+        bp.sbbnnls_step_batch(D, b_all, w_all, states)
+
+    single_states = [life.new_state(dev) for _ in inst]
+
+    def sequential():
+        for sp, b, w, st in zip(singles, bs, ws, single_states):
+            sp.sbbnnls_step(D, b, w, st)
+
+    for _ in range(args.warmup):
+        batched()
+        sequential()
+    t_batched = _time_ms(batched, args.steps)
+    t_seq = _time_ms(sequential, args.steps)
+    # the same iteration captured once and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched()
+    t_graph = _time_ms(graph.replay, args.steps)
+    out = {"metric": "Phi nonzeros/s for one batched SBB-NNLS iteration over all instances (hipGraph replay)",
+           "value": round(nnz * 3.5 / 2 / (t_graph / 1e3), 1), "unit": "nnz/s", "higher_is_better": True,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_graph, 4), "ms_per_step_eager": round(t_batched, 4),
+           "ms_per_step_sequential_plans": round(t_seq, 4), "speedup_vs_sequential": round(t_seq / t_graph, 3),
+           "schedule": policy, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(inst)} uneven synthetic connectomes sharing D", "nnz": nnz,
+                      "n_voxels": [c.n_voxels for c in inst], "n_fascicles": [c.n_fascicles for c in inst],
+                      "scale": args.batch_scale}}
+    for sp in singles:
+        sp.close()
+    bp.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,11 +352,27 @@ def main():
                     help="voxel processing order of the plan: Morton order of the grid coordinates, or voxel index")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (calibrates the HBM byte counters)")
+    ap.add_argument("--workload", default="sbb", choices=["sbb", "adam", "batched"],
+                    help="sbb: the headline SBB-NNLS iteration; adam: dictionary learning steps on the mid "
+                         "connectome; batched: uneven instances sharing D")
+    ap.add_argument("--adam-steps", type=int, default=200)
+    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="size factor of the batched instances")
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="only summarize rocprofv3 outputs (trace/, fetch/, write/, tcc/, copyf/, copyw/) into profiles/")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize, args.config)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the voxel-sharded design is described, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "adam":
+        bench_adam(args)
+        return
+    if args.workload == "batched":
+        bench_batched(args)
         return
     if args.copy_probe:
         import torch
