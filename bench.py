@@ -456,7 +456,15 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(bw / HBM_PEAK_GBS, 4)}
+    # achievable stream bandwidth on this GPU: a plain 1 GiB device copy (read + write)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t_copy = _time_ms(lambda: dst.copy_(src), 5)
+    copy_gbs = 2.0 * src.numel() * 4 / (t_copy / 1e3) / 1e9
+    del src, dst
     roof.update({"traffic": recorded_traffic(args.config, dom), "kernel": dom, "avg_ms": round(avg[dom], 4),
+                 "achievable_copy_GBs": round(copy_gbs, 1),
                  "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
                  "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})
 
