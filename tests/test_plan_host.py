@@ -197,3 +197,14 @@ def test_batch_rejects_nonzero_across_instances():
     with pytest.raises(life.LifeError) as e:
         life.plan_host_batch(None, raw=tuple(bad))
     assert e.value.status == 1
+
+
+def test_batch_plan_needs_chunked_geometry():
+    """Batched plans need N_theta <= 128 (checked before any device is touched)."""
+    a = synth.random_coo(129, 5, 40, 10, 200, seed=1)
+    b = synth.random_coo(129, 5, 30, 12, 150, seed=2)
+    for c in (a, b):
+        c.voxel_xyz = np.zeros((c.n_voxels, 3), np.int16)
+    with pytest.raises(life.LifeError) as e:
+        life.Plan.batch([a, b])
+    assert e.value.status == 1
