@@ -106,8 +106,9 @@ std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePo
 // The padded arrays of the chunked layout from the canonical DSC-order arrays:
 // pad entries get value 0, the atom of the entry before them and fascicle rank 0.  The WC
 // pass-1 output z uses its own order inside each chunk's range: the chunk's
-// entries in WC order (so one fascicle's entries in one chunk are adjacent),
-// then its pad entries.  z_pos[q] = z position of padded entry q;
+// entries tile by tile, in WC order inside a tile (so one fascicle's entries of
+// one tile in one chunk are adjacent, and the writes of one tile's pass stay in
+// one sub-range), then its pad entries.  z_pos[q] = z position of padded entry q;
 // wc_perm_z[j] = z position of WC slot j.  Returns the padded length, or -1 if it
 // exceeds the 32-bit position limit.
 int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,

@@ -372,18 +372,33 @@ int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, con
                     for (int64_t q = beg + n_real; q < end; ++q) atom_c[(size_t)q] = atom_c[(size_t)q - 1];
                 }
             }
-    // z order: inside each chunk's range, its entries in WC order, then its pads
+    // z order: inside each chunk's range, its entries by tile, in WC order inside a tile, then its pads
     std::vector<int64_t> next((size_t)n_chunks + 1);
     for (int c = 0; c < n_chunks; ++c) next[c] = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];
     next[n_chunks] = n_pad;
     const std::vector<int64_t> chunk_end(next.begin() + 1, next.end());
+    std::vector<int64_t> tnext((size_t)n_chunks * T, 0);
+    for (int64_t p = 0; p < d->nnz; ++p) {
+        const int32_t v = voxel_of_dsc[p];
+        const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
+        tnext[(size_t)c * T + atom_v[p] / tg.tile_atoms]++;
+    }
+    for (int c = 0; c < n_chunks; ++c) {
+        int64_t b = next[c];
+        for (int t = 0; t < T; ++t) {
+            const int64_t n = tnext[(size_t)c * T + t];
+            tnext[(size_t)c * T + t] = b;
+            b += n;
+        }
+        next[c] = b;   // pads follow the real entries
+    }
     z_pos.assign((size_t)n_pad, -1);
     wc_perm_z.resize((size_t)d->nnz);
     for (int64_t j = 0; j < d->nnz; ++j) {
         const int32_t p = wc_perm[j];
         const int32_t v = voxel_of_dsc[p];
         const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
-        const int32_t zp = static_cast<int32_t>(next[c]++);
+        const int32_t zp = static_cast<int32_t>(tnext[(size_t)c * T + atom_v[p] / tg.tile_atoms]++);
         z_pos[(size_t)cpos[(size_t)p]] = zp;
         wc_perm_z[(size_t)j] = zp;
     }
