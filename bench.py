@@ -50,6 +50,8 @@ PROFILE_COMMANDS = {
              "python3 $R/bench.py --copy-probe",
 }
 KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_chunk", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
+# profiling classes launched by the same kernel (the second WC of even iterations)
+KIND_GROUPS = {"dsc": ("dsc",), "wc_z": ("wc_z", "wc_z_2nd"), "wc_sum": ("wc_sum", "wc_sum_2nd")}
 
 
 def log(msg: str):
@@ -443,9 +445,13 @@ def main():
     t_dsc = avg["dsc"]
     t_wc = avg["wc_z"] + avg["wc_sum"]
 
-    dom = max(("dsc", "wc_z", "wc_sum"), key=lambda k: ms[k])
+    # the kernel with the largest total time over the timed steps
+    tot = {k: sum(ms[x] for x in g) for k, g in KIND_GROUPS.items()}
+    launches = {k: sum(cnt[x] for x in g) for k, g in KIND_GROUPS.items()}
+    dom = max(tot, key=lambda k: tot[k])
+    dom_ms = tot[dom] / max(launches[dom], 1)
     by, fl = algorithmic(dom, d)
-    t_s = avg[dom] / 1e3
+    t_s = dom_ms / 1e3
     bw = by / t_s / 1e9
     tf = fl / t_s / 1e12
     t_hbm = by / (HBM_PEAK_GBS * 1e9)
@@ -463,7 +469,7 @@ def main():
     t_copy = _time_ms(lambda: dst.copy_(src), 5)
     copy_gbs = 2.0 * src.numel() * 4 / (t_copy / 1e3) / 1e9
     del src, dst
-    roof.update({"traffic": recorded_traffic(args.config, dom), "kernel": dom, "avg_ms": round(avg[dom], 4),
+    roof.update({"traffic": recorded_traffic(args.config, dom), "kernel": dom, "avg_ms": round(dom_ms, 4),
                  "achievable_copy_GBs": round(copy_gbs, 1),
                  "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
                  "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})

@@ -335,109 +335,185 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     if (part) block_sum_store<kWG>(sq, part, chunk);
 }
 
+// ----------------------------------------------------------------------------- WC pass 1 on the matrix cores
+// For one chunk and one atom tile every needed projection <D[:, a], y[:, v]> is an
+// entry of the dense block P = D_tile^T Y_chunk (atoms x 64 voxel slots), formed on
+// v_mfma_f32_32x32x16_f16; each nonzero then costs one LDS lookup,
+// z_c = phi_c P[atom_c][slot_c], instead of an N_theta-long dot product.
+// FP32 operands enter the matrix cores as FP16 pairs: a column is scaled by a power
+// of two 2^k that puts its largest magnitude in [2^13, 2^14), and each scaled value
+// x becomes hi = fp16(x), lo = fp16(x - hi), so x = hi + lo up to 2^-22 |x| (for
+// values so small that lo is subnormal, up to 2^-38 of the column maximum).
+// The product takes hi*hi + (hi*lo + lo*hi) with FP32 accumulation (the dropped
+// lo*lo term is below 2^-22 relative), and the scales (per atom for D, per voxel
+// slot for y) are undone exactly on P.  Every element of P depends only on its own
+// atom column and voxel column, so results do not depend on the chunking.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kPS = 64;   // LDS row stride of P (floats): one row per atom, one column per slot
+
+// exponent k with m 2^k in [2^13, 2^14) (0 when m is zero or not finite), clamped so
+// that 2^-k stays a normal float
+__device__ __forceinline__ int split_exp(float m)
+{
+    if (!(m > 0.f) || !(m <= 3.4028234e38f)) return 0;
+    int e;
+    (void)frexpf(m, &e);
+    return min(120, max(-120, 14 - e));
+}
+
+__device__ __forceinline__ void split_f16(float x, _Float16 &hi, _Float16 &lo)
+{
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);   // x - hi is exact in FP32
+}
+
+// A operands of P = D_tile^T Y: one wave per (tile t, atom block ab of 32, row r);
+// for a = t TA + 32 ab + r and theta = 16 ks + 8 hf + i, half i of
+// frag[(((t AB + ab) KS + ks) 2 + part) 64 + 32 hf + r] is part 0 (hi) or 1 (lo) of
+// 2^{k_a} D[theta][a] (zero outside the tile, the dictionary or N_theta), and
+// dscale[(t AB + ab) 32 + r] = 2^{-k_a}.  N_theta <= 128.
+__global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D, h8 *__restrict__ frag,
+                                                      float *__restrict__ dscale, int nth, int na, int T, int TA,
+                                                      int AB, int KS, Gate gate)
+{
+    if (gated_off(gate)) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= T * AB * 32) return;   // uniform per wave
+    const int t = i / (AB * 32), rem = i - t * AB * 32, ab = rem / 32, r = rem % 32;
+    const int al = 32 * ab + r, a = t * TA + al;
+    const bool ok = al < TA && a < na;
+    const float x0 = (ok && lane < nth) ? D[(size_t)a * nth + lane] : 0.f;
+    const float x1 = (ok && lane + 64 < nth) ? D[(size_t)a * nth + lane + 64] : 0.f;
+    float m = fmaxf(fabsf(x0), fabsf(x1));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const int e = split_exp(m);
+    if (lane == 0) dscale[i] = ldexpf(1.f, -e);
+    _Float16 *f = reinterpret_cast<_Float16 *>(frag);
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int th = lane + 64 * hh;
+        if (th < 16 * KS) {
+            const int ks = th / 16, hf = (th % 16) / 8, q = th % 8;
+            const size_t base = ((size_t)((t * AB + ab) * KS + ks) * 2 * 64 + 32 * hf + r) * 8 + q;
+            _Float16 hi, lo;
+            split_f16(ldexpf(hh ? x1 : x0, e), hi, lo);
+            f[base] = hi;
+            f[base + 64 * 8] = lo;
+        }
+    }
+}
+
 // WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the
 // chunked layout (pad entries give 0).  z_pos keeps each chunk's values inside the
-// chunk's own range, in WC order, so pass 2 reads one fascicle's values in a chunk
-// as one contiguous run.
-template <int NC>
-__global__ __launch_bounds__(kWG) void k_wcz_chunk(const int32_t *__restrict__ chunk_map,
-                                                   const int32_t *__restrict__ chunk_vox,
-                                                   const int32_t *__restrict__ wave_work,
-                                                   const int16_t *__restrict__ atom,
-                                                   const float *__restrict__ phi,
-                                                   const int32_t *__restrict__ z_pos,
-                                                   const float *__restrict__ D,
-                                                   const float *__restrict__ y,
-                                                   float *__restrict__ z, int nth, int na, int T, int TA,
-                                                   bool vec, Gate gate)
+// chunk's own range, grouped by tile and in WC order inside a tile, so pass 2 reads
+// one fascicle's values in a chunk as short contiguous runs.
+// LDS: P [32 AB][kPS] floats, Y hi and lo [64 slots][YS] halves (YS = 16 KS + 8:
+// conflict-free 16-byte reads along theta), the 64 slot scales.  Waves 0..AB-1
+// each form one 32-atom block of P for both 32-slot halves; then every wave looks
+// up its own slots' nonzeros.
+__global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ chunk_map,
+                                                  const int32_t *__restrict__ chunk_vox,
+                                                  const int32_t *__restrict__ wave_work,
+                                                  const int16_t *__restrict__ atom,
+                                                  const float *__restrict__ phi,
+                                                  const int32_t *__restrict__ z_pos,
+                                                  const h8 *__restrict__ frag,
+                                                  const float *__restrict__ dscale,
+                                                  const float *__restrict__ y,
+                                                  float *__restrict__ z, int nth, int T, int TA, int AB,
+                                                  int KS, Gate gate)
 {
     if (gated_off(gate)) return;   // uniform over the grid
     extern __shared__ float4 lds4[];
-    float *lds = reinterpret_cast<float *>(lds4);
-    constexpr int ROW = NC * 32;
-    constexpr int PER = NC * 2;
+    float *P = reinterpret_cast<float *>(lds4);
+    const int YS = 16 * KS + 8;
+    _Float16 *Yh = reinterpret_cast<_Float16 *>(P + AB * 32 * kPS);
+    _Float16 *Yl = Yh + kChunkVoxels * YS;
+    float *yscale = reinterpret_cast<float *>(Yl + kChunkVoxels * YS);
     const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane / kGL, l16 = lane % kGL;
-    const int mypos = kSE * l16 + g;
-    float yv[kWaveVoxels][PER];
+
+    // the chunk's y columns, each scaled by its own power of two and split
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
-        const int v = uni(chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + j]);
+        const int slot = wave * kWaveVoxels + j;
+        const int v = uni(chunk_vox[chunk * kChunkVoxels + slot]);
+        float x0 = 0.f, x1 = 0.f;
+        if (v >= 0) {
+            if (lane < nth) x0 = y[(size_t)v * nth + lane];
+            if (lane + 64 < nth) x1 = y[(size_t)v * nth + lane + 64];
+        }
+        float m = fmaxf(fabsf(x0), fabsf(x1));
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int th = 32 * cc + 2 * l16 + q;
-                yv[j][2 * cc + q] = (v >= 0 && th < nth) ? y[(size_t)v * nth + th] : 0.f;
-            }
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        const int e = split_exp(m);
+        if (lane == 0) yscale[slot] = ldexpf(1.f, -e);
+        if (lane < 16 * KS) split_f16(ldexpf(x0, e), Yh[slot * YS + lane], Yl[slot * YS + lane]);
+        if (lane + 64 < 16 * KS) split_f16(ldexpf(x1, e), Yh[slot * YS + lane + 64], Yl[slot * YS + lane + 64]);
     }
 
     for (int t = 0; t < T; ++t) {
         const int a0 = t * TA;
-        __syncthreads();
-        stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
-        const WaveRange R(wave_work, chunk, t, T, wave);
-        __syncthreads();
-        if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
-        int ix = R.p[0] + (mypos < R.p[kWaveVoxels] - R.p[0] ? mypos : 0);
-        int a_n = atom[ix], zp_n = z_pos[ix];
-        float ph_n = phi[ix];
+        __syncthreads();   // Y is staged / the previous tile's lookups are done with P
+        if (wave < AB) {
+            // hi*hi and the two correction products accumulate separately: the matrix
+            // cores' FP32 accumulation is biased toward zero by about 2^-24 of each
+            // partial sum, and a bias on the large hi*hi sums would add up coherently in
+            // sums over many fascicles (<w, M^T y> drifts by ~1e-5 of itself otherwise)
+            f32x16 c0 = {}, c1 = {}, e0 = {}, e1 = {};
+            const h8 *fa = frag + (size_t)(t * AB + wave) * KS * 2 * 64 + lane;
+            const int col = lane & 31, kh = 8 * (lane >> 5);
+            for (int ks = 0; ks < KS; ++ks) {
+                const h8 ah = fa[(2 * ks) * 64], al = fa[(2 * ks + 1) * 64];
+                const int k0 = 16 * ks + kh;
+                const h8 bh0 = *reinterpret_cast<const h8 *>(Yh + col * YS + k0);
+                const h8 bh1 = *reinterpret_cast<const h8 *>(Yh + (32 + col) * YS + k0);
+                const h8 bl0 = *reinterpret_cast<const h8 *>(Yl + col * YS + k0);
+                const h8 bl1 = *reinterpret_cast<const h8 *>(Yl + (32 + col) * YS + k0);
+                c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh0, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh1, c1, 0, 0, 0);
+                e0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl0, e0, 0, 0, 0);
+                e1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl1, e1, 0, 0, 0);
+                e0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh0, e0, 0, 0, 0);
+                e1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh1, e1, 0, 0, 0);
+            }
+            // accumulator r of lane l holds (atom row 8 (r/4) + 4 (l/32) + r%4, slot l%32)
+            const float s0 = yscale[col], s1 = yscale[32 + col];
+            const float *ds = dscale + (size_t)(t * AB + wave) * 32;
 #pragma unroll
-        for (int j = 0; j < kWaveVoxels; ++j) {
-            for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
-                const int m = min(kBatch, R.p[j + 1] - b);
-                const int a_c = a_n, zp_c = zp_n;
-                const float ph_c = ph_n;
-                int nxt = b + kBatch < R.p[j + 1] ? b + kBatch : R.p[j + 1];
-                nxt = nxt + mypos < R.p[kWaveVoxels] ? nxt + mypos : R.p[0];
-                a_n = atom[nxt];
-                zp_n = z_pos[nxt];
-                ph_n = phi[nxt];
-                const bool valid = mypos < m;
-                const int aoff = valid ? (a_c - a0) * ROW : 0;
-                float p[kGL];
-#define LIFE_WCZ_STEP(K)                                                                  \
-    {                                                                                     \
-        const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
-        float q0 = 0.f;                                                                   \
-        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
-            const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
-            q0 = fmaf(d.x, yv[j][2 * cc + 0], q0);                                        \
-            q0 = fmaf(d.y, yv[j][2 * cc + 1], q0);                                        \
-        }                                                                                 \
-        p[K] = q0;                                                                        \
-    }
-                if (m == kBatch) {
-                    LIFE_WCZ_STEP(0) LIFE_WCZ_STEP(1) LIFE_WCZ_STEP(2) LIFE_WCZ_STEP(3)
-                    LIFE_WCZ_STEP(4) LIFE_WCZ_STEP(5) LIFE_WCZ_STEP(6) LIFE_WCZ_STEP(7)
-                    LIFE_WCZ_STEP(8) LIFE_WCZ_STEP(9) LIFE_WCZ_STEP(10) LIFE_WCZ_STEP(11)
-                    LIFE_WCZ_STEP(12) LIFE_WCZ_STEP(13) LIFE_WCZ_STEP(14) LIFE_WCZ_STEP(15)
-                } else {
-                    const int ns = m / kSE;
-#define LIFE_WCZ_GSTEP(K) p[K] = 0.f; if (K < ns) LIFE_WCZ_STEP(K)
-                    LIFE_WCZ_GSTEP(0) LIFE_WCZ_GSTEP(1) LIFE_WCZ_GSTEP(2) LIFE_WCZ_GSTEP(3)
-                    LIFE_WCZ_GSTEP(4) LIFE_WCZ_GSTEP(5) LIFE_WCZ_GSTEP(6) LIFE_WCZ_GSTEP(7)
-                    LIFE_WCZ_GSTEP(8) LIFE_WCZ_GSTEP(9) LIFE_WCZ_GSTEP(10) LIFE_WCZ_GSTEP(11)
-                    LIFE_WCZ_GSTEP(12) LIFE_WCZ_GSTEP(13) LIFE_WCZ_GSTEP(14) LIFE_WCZ_GSTEP(15)
-#undef LIFE_WCZ_GSTEP
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                const float d = ds[row];
+                P[(32 * wave + row) * kPS + col] = ((c0[r] + e0[r]) * d) * s0;
+                P[(32 * wave + row) * kPS + 32 + col] = ((c1[r] + e1[r]) * d) * s1;
+            }
+        }
+        __syncthreads();
+        const WaveRange R(wave_work, chunk, t, T, wave);
+        const int p1 = R.p[1], p2 = R.p[2], p3 = R.p[3], pe = R.p[kWaveVoxels];
+        for (int b = R.p[0]; b < pe; b += 4 * 64) {
+            int aa[4], zz[4];
+            float ff[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = b + 64 * u + lane;
+                const int ix = idx < pe ? idx : R.p[0];
+                aa[u] = atom[ix];
+                ff[u] = phi[ix];
+                zz[u] = z_pos[ix];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = b + 64 * u + lane;
+                if (idx < pe) {
+                    const int slot = wave * kWaveVoxels + (idx >= p1) + (idx >= p2) + (idx >= p3);
+                    z[zz[u]] = ff[u] * P[(aa[u] - a0) * kPS + slot];
                 }
-#undef LIFE_WCZ_STEP
-                // transpose-reduce across the 16 lanes of each group (fixed butterfly):
-                // afterwards lane (g, l16) holds the full dot of step l16 = entry mypos
-#define LIFE_TR_STAGE(H)                                                                  \
-    {                                                                                     \
-        const bool hi = (l16 & H) != 0;                                                   \
-        _Pragma("unroll") for (int k = 0; k < H; ++k) {                                   \
-            const float send = hi ? p[k] : p[k + H];                                      \
-            const float keep = hi ? p[k + H] : p[k];                                      \
-            p[k] = keep + xor16<H>(send, l16);                                            \
-        }                                                                                 \
-    }
-                LIFE_TR_STAGE(8) LIFE_TR_STAGE(4) LIFE_TR_STAGE(2) LIFE_TR_STAGE(1)
-#undef LIFE_TR_STAGE
-                if (valid) z[zp_c] = ph_c * p[0];
             }
         }
     }
@@ -962,6 +1038,11 @@ struct life_plan_s {
     float *phi_c = nullptr;       // [n_pad]
     int32_t *z_pos = nullptr;     // [n_pad] z position of each padded entry
     int32_t *wc_perm_z = nullptr; // [nnz] z position of each WC slot
+    // WC pass 1 on the matrix cores: split D^T operands (k_split_dt) and the LDS size
+    int dt_ab = 0, dt_ks = 0;     // atom blocks of 32 per tile, k-steps of 16 theta
+    size_t wcz_lds = 0;
+    h8 *dt_frag = nullptr;        // [n_tiles][dt_ab][dt_ks][2][64]
+    float *dt_scale = nullptr;    // [n_tiles][dt_ab][32]
     // fascicles are processed in rank order (fas_v holds ranks)
     int32_t *fas_rank = nullptr;  // [Nf] rank of each fascicle
     int32_t *fas_ext = nullptr;   // [Nf] fascicle of each rank
@@ -1019,7 +1100,7 @@ hipError_t dalloc(T **p, int64_t n)
 void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c, p->fas_c,
-                    p->phi_c, p->z_pos, p->wc_perm_z, p->fas_rank, p->fas_ext,
+                    p->phi_c, p->z_pos, p->wc_perm_z, p->dt_frag, p->dt_scale, p->fas_rank, p->fas_ext,
                     p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
                     p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
@@ -1116,8 +1197,7 @@ hipError_t allow_lds()
 {
     const int bytes = life::kLdsBudget;
     const void *fns[] = {(const void *)k_dsc_chunk<1>, (const void *)k_dsc_chunk<2>, (const void *)k_dsc_chunk<3>,
-                         (const void *)k_dsc_chunk<4>, (const void *)k_wcz_chunk<1>, (const void *)k_wcz_chunk<2>,
-                         (const void *)k_wcz_chunk<3>, (const void *)k_wcz_chunk<4>, (const void *)k_dd_chunk<1>,
+                         (const void *)k_dsc_chunk<4>, (const void *)k_wcz_mfma, (const void *)k_dd_chunk<1>,
                          (const void *)k_dd_chunk<2>, (const void *)k_dd_chunk<3>, (const void *)k_dd_chunk<5>,
                          (const void *)k_dd_chunk<9>, (const void *)k_dd_chunk<12>};
     for (const void *f : fns) {
@@ -1156,22 +1236,23 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
 }
 
 life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, const int32_t *gmap,
-                       double *part, Gate gate, hipStream_t s)
+                       double *part, Gate gate, hipStream_t s, bool split_d = true)
 {
     const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
     life_status st = LIFE_OK;
     if (nv > 0 && p->dims.nnz > 0) {
         const int kind = gate.st ? LIFE_K_WC_Z_2ND : LIFE_K_WC_Z;
         if (chunked(p)) {
-            const int nc = p->tile.row_floats / 32;
-            const size_t lds = tile_lds_bytes(p);
+            // split_d = false: D was split by an earlier call of the same enqueue sequence
+            const int T = p->tile.n_tiles, AB = p->dt_ab, KS = p->dt_ks, TA = p->tile.tile_atoms;
             st = launch(p, kind, s, [&] {
-                LIFE_DISPATCH_NC(nc, k_wcz_chunk, p->chunk_grid, kWG, lds, s>>>(p->chunk_map, p->chunk_vox,
-                                                                               p->wave_work, p->atom_c,
-                                                                               p->phi_c, p->z_pos, D, y, p->z, nth,
-                                                                               p->dims.n_atoms, p->tile.n_tiles,
-                                                                               p->tile.tile_atoms, vec_tile(p, D),
-                                                                               gate))
+                if (split_d)
+                    k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, p->dt_frag, p->dt_scale,
+                                                                                         nth, p->dims.n_atoms, T, TA,
+                                                                                         AB, KS, gate);
+                k_wcz_mfma<<<p->chunk_grid, kWG, p->wcz_lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work, p->atom_c,
+                                                                  p->phi_c, p->z_pos, p->dt_frag, p->dt_scale, y, p->z,
+                                                                  nth, T, TA, AB, KS, gate);
             });
         } else {
             const int grid = cdiv(nv, kSegPerBlock);
@@ -1376,10 +1457,15 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         const int nb_blocks = (d.n_theta + 15) / 16 * (p->dd_tap / 16);
         p->dd_nbw = dd_nbw_variant((nb_blocks + kChunkWaves - 1) / kChunkWaves);
         dd_floats = (int64_t)T * p->dd_groups * p->dd_tap * ((d.n_theta + 15) / 16 * 16);
+        p->dt_ab = (tg.tile_atoms + 31) / 32;
+        p->dt_ks = (d.n_theta + 15) / 16;
+        p->wcz_lds = (size_t)p->dt_ab * 32 * kPS * sizeof(float) +
+                     (size_t)2 * kChunkVoxels * (16 * p->dt_ks + 8) * sizeof(_Float16) + kChunkVoxels * sizeof(float);
         if (p->dd_nbw < 0 ||
-            (int64_t)(p->dd_tap + (d.n_theta + 15) / 16 * 16) * kPsiStride * 4 > life::kLdsBudget) {
+            (int64_t)(p->dd_tap + (d.n_theta + 15) / 16 * 16) * kPsiStride * 4 > life::kLdsBudget ||
+            p->dt_ab > kChunkWaves || p->dt_ks > 8 || p->wcz_lds > (size_t)life::kLdsBudget) {
             delete p;
-            return LIFE_EINVAL;   // cannot happen: tiles hold at most kMaxTileAtoms atoms
+            return LIFE_EINVAL;   // cannot happen: tiles hold at most kMaxTileAtoms atoms, N_theta <= 128
         }
     }
     hipError_t e = hipSuccess;
@@ -1396,6 +1482,10 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     chk(dalloc(&p->phi_c, n_pad));
     chk(dalloc(&p->z_pos, (int64_t)zpos.size()));
     chk(dalloc(&p->wc_perm_z, (int64_t)wperm_z.size()));
+    if (n_chunks > 0) {
+        chk(dalloc(&p->dt_frag, (int64_t)tg.n_tiles * p->dt_ab * p->dt_ks * 2 * 64));
+        chk(dalloc(&p->dt_scale, (int64_t)tg.n_tiles * p->dt_ab * 32));
+    }
     chk(dalloc(&p->fas_rank, d.n_fascicles));
     chk(dalloc(&p->fas_ext, d.n_fascicles));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
@@ -1582,7 +1672,8 @@ life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float
     if ((st = enqueue_dsc(plan, D, q, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
     // v'' = M^T v', ||v''||^2, on the iterations of the second alpha form (even i
     // in Algorithm 1, odd i in eqs. 7-8); the kernels test the parity on the device
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, Gate{state, lagged ? 1 : 0}, s)) != LIFE_OK)
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, Gate{state, lagged ? 1 : 0}, s, false)) !=
+        LIFE_OK)
         return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
         k_alpha<<<1, kAlphaThreads, 0, s>>>(p_r, nb_dsc, p_gt, nb_mask, lagged ? p_q : nullptr, nb_mask, p_vp, nb_dsc,
@@ -1623,7 +1714,8 @@ life_status enqueue_sbb_batch(life_plan_s *plan, const float *D, const float *b,
     }
     if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
     // instances advance together: the first instance's parity gates the second WC
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, nullptr, Gate{states, 0}, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, nullptr, Gate{states, 0}, s, false)) != LIFE_OK)
+        return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
         k_alpha_batch<<<plan->n_inst, kAlphaThreads, 0, s>>>(p_r, p_vp, plan->inst_chunk, plan->gt, plan->vpp,
                                                              plan->inst_rank, states);

@@ -99,15 +99,21 @@ def test_wc_parity(name, dev):
     assert relerr(_np(g), op.wc(c.noise)) <= TOL, name
 
 
-@pytest.mark.parametrize("name", ["tiny", "mid", "r100"])
+@pytest.mark.parametrize("name", ["tiny", "mid", "r100", "r96big"])
 def test_adjoint_identity_fp32(name, dev):
+    """<M w, y> = <w, M^T y> for the device DSC and WC, relative to |<M w, y>| (a
+    random-sign y: the sums cancel, so a rounding bias in either product shows), and
+    <w, M^T (M w)> = ||M w||^2."""
     c, op, plan = problem(name, dev)
     D = _t(c.D, dev)
     w = _t(c.w0, dev)
     y = _t(c.noise, dev)
-    lhs = float(_np(plan.dsc(D, w)) @ _np(y))
+    mw = plan.dsc(D, w)
+    lhs = float(_np(mw) @ _np(y))
     rhs = float(_np(w) @ _np(plan.wc(D, y)))
     assert abs(lhs - rhs) <= TOL * abs(lhs)
+    n2, rhs2 = float(_np(mw) @ _np(mw)), float(_np(w) @ _np(plan.wc(D, mw)))
+    assert abs(n2 - rhs2) <= TOL * n2
 
 
 @pytest.mark.parametrize("name", ["mid", "r5dup"])
@@ -117,6 +123,39 @@ def test_bitwise_deterministic(name, dev):
     a1, a2 = plan.dsc(D, w), plan.dsc(D, w)
     b1, b2 = plan.wc(D, y), plan.wc(D, y)
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+def test_interleaved_calls_on_one_plan(dev):
+    """DSC and WC calls on one plan (one workspace) in any order give the results
+    of calls on a fresh plan."""
+    c, op, plan = problem("mid", dev)
+    D, w, y = _t(c.D, dev), _t(c.w0, dev), _t(c.noise, dev)
+    a1 = plan.dsc(D, w)
+    b1 = plan.wc(D, y)
+    a2 = plan.dsc(D, w)
+    b2 = plan.wc(D, y)
+    b3 = plan.wc(D, y)
+    a3 = plan.dsc(D, y[:c.n_fascicles].abs())
+    assert torch.equal(a1, a2) and torch.equal(b1, b2) and torch.equal(b2, b3)
+    assert relerr(_np(a3), op.dsc(np.abs(c.noise[:c.n_fascicles]).astype(np.float32))) <= TOL
+
+
+@pytest.mark.parametrize("name", ["mid", "r129", "empty"])
+def test_profile_counts_launches(name, dev):
+    c, op, plan = problem(name, dev)
+    D, w, y = _t(c.D, dev), _t(c.w0, dev), _t(c.noise, dev)
+    plan.profile_read()
+    plan.profile_enable(True)
+    plan.dsc(D, w)
+    plan.wc(D, y)
+    torch.cuda.synchronize()
+    plan.profile_enable(False)
+    ms, cnt = plan.profile_read()
+    launched = 1 if c.nnz > 0 else 0
+    # life_dsc first gathers w into the plan's fascicle (rank) order
+    assert cnt["permute"] == 1 and cnt["dsc"] == 1, cnt
+    assert cnt["wc_z"] == launched and cnt["wc_sum"] == 1, cnt
+    assert all(v >= 0.0 for v in ms.values()) and sum(cnt.values()) == 3 + launched
 
 
 def test_outputs_overwritten(dev):
