@@ -49,7 +49,7 @@ PROFILE_COMMANDS = {
     "copyw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/copyw -o run -- "
              "python3 $R/bench.py --copy-probe",
 }
-KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_chunk", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
+KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_mfma", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
 # profiling classes launched by the same kernel (the second WC of even iterations)
 KIND_GROUPS = {"dsc": ("dsc",), "wc_z": ("wc_z", "wc_z_2nd"), "wc_sum": ("wc_sum", "wc_sum_2nd")}
 
