@@ -99,9 +99,10 @@ const char *life_status_str(life_status s);
  * i.e. by fascicle, for WC) as two permutations with their segment offsets.
  * Voxels are processed in a locality order: voxel index order, or, when grid
  * coordinates are given, the Morton (Z-order) sequence of the coordinates (ties
- * by index).  Fascicles are ranked by the mean processing position of the voxels
- * they cross (ties by fascicle index, empty fascicles last), so that fascicles
- * handled together touch nearby voxels.
+ * by index).  Fascicles are ranked by the Z-order (bit interleave) of the first
+ * and last processing positions of the voxels they cross (ties by fascicle index,
+ * empty fascicles last), so that fascicles crossing the same voxels have nearby
+ * ranks.
  *   atom, voxel, fascicle: host, nnz entries each (input COO order).
  *   voxel_xyz (host, 3*n_voxels, optional): non-negative (x, y, z) grid
  *                                   coordinates of each voxel, or NULL.

@@ -1366,21 +1366,21 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         ppos.resize((size_t)d.n_voxels);
         pvox.resize((size_t)n_pos);
         life::voxel_order(&d, voxel_xyz, n_inst, vox_off, ppos.data(), pvox.data());
-        std::vector<double> empty_key;
+        std::vector<int32_t> empty_end;
         if (batched) {
             // fascicles without nonzeros rank at the end of their own instance
-            empty_key.resize((size_t)d.n_fascicles);
+            empty_end.resize((size_t)d.n_fascicles);
             int32_t base = 0;
             for (int k = 0; k < n_inst; ++k) {
                 base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
                 ichunk[(size_t)k + 1] = base / kChunkVoxels;
-                for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_key[(size_t)f] = base;
+                for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_end[(size_t)f] = base;
             }
         } else {
             ichunk[1] = n_chunks;
         }
         st = life::plan_host(&d, atom, voxel, fascicle, (voxel_xyz || batched) ? ppos.data() : nullptr, n_pos,
-                             batched ? empty_key.data() : nullptr, perm.data(), vptr.data(), rank.data(),
+                             batched ? empty_end.data() : nullptr, perm.data(), vptr.data(), rank.data(),
                              wperm.data(), fptr.data());
         if (st != LIFE_OK) return st;
         for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;

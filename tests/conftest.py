@@ -55,19 +55,44 @@ def morton_positions(xyz):
     return pos
 
 
+def fascicle_keys(fascicle, vpp, n_fascicles, empty_end=None):
+    """Rank keys of the fascicles: 2 * Z(lo, hi), where lo, hi are the first and last
+    processing positions of a fascicle's voxels and Z puts bit i of lo at bit 2i and
+    bit i of hi at bit 2i+1; a fascicle without nonzeros gets 2 * Z(e, e) + 1 with
+    e = empty_end - 1 when its block end is given, else the largest key."""
+    lo = np.full(n_fascicles, np.iinfo(np.int64).max, np.int64)
+    hi = np.full(n_fascicles, -1, np.int64)
+    np.minimum.at(lo, fascicle, vpp)
+    np.maximum.at(hi, fascicle, vpp)
+    has = hi >= 0
+    a = np.where(has, lo, 0).astype(np.uint64)
+    b = np.where(has, hi, 0).astype(np.uint64)
+    if empty_end is not None:
+        e = np.asarray(empty_end, np.int64) - 1
+        a = np.where(has, a, e.astype(np.uint64))
+        b = np.where(has, b, e.astype(np.uint64))
+    z = np.zeros(n_fascicles, np.uint64)
+    for i in range(32):
+        one = np.uint64(1)
+        z |= ((a >> np.uint64(i)) & one) << np.uint64(2 * i)
+        z |= ((b >> np.uint64(i)) & one) << np.uint64(2 * i + 1)
+    key = z * np.uint64(2)
+    if empty_end is None:
+        return np.where(has, key, np.iinfo(np.uint64).max)
+    return np.where(has, key, key + np.uint64(1))
+
+
 def reference_plan(c, xyz=None):
     """The restructuring plan computed independently with numpy.lexsort.
 
     DSC order (voxel, atom, fascicle, input position); voxel processing positions
-    pp (identity, or Morton order of xyz); fascicle ranks by mean pp of their
-    voxels (empty fascicles last, ties by index); WC order (rank, pp, atom, input
-    position) given as DSC positions; segment offsets of both."""
+    pp (identity, or Morton order of xyz); fascicle ranks by fascicle_keys (empty
+    fascicles last, ties by index); WC order (rank, pp, atom, input position) given
+    as DSC positions; segment offsets of both."""
     pos = np.arange(c.nnz)
     pp = np.arange(c.n_voxels) if xyz is None else morton_positions(xyz)
     dsc = np.lexsort((pos, c.fascicle, c.atom, c.voxel))
-    cnt = np.bincount(c.fascicle, minlength=c.n_fascicles)
-    tot = np.bincount(c.fascicle, weights=pp[c.voxel].astype(np.float64), minlength=c.n_fascicles)
-    key = np.where(cnt > 0, tot / np.maximum(cnt, 1), np.inf)
+    key = fascicle_keys(c.fascicle, pp[c.voxel], c.n_fascicles)
     order = np.argsort(key, kind="stable")
     rank = np.empty(c.n_fascicles, np.int64)
     rank[order] = np.arange(c.n_fascicles)

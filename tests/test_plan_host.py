@@ -68,6 +68,20 @@ def test_morton_positions_pinned():
     assert np.array_equal(morton_positions(pts), [3, 2, 1, 0])
 
 
+def test_fascicle_rank_key_pinned():
+    """Fascicles rank by the Z-order of (first, last) voxel position, worked by hand
+    on 8 voxels in index order: f2 spans (1, 1) -> Z = 0b11 = 3, f0 spans (3, 4) ->
+    bits of 3 at 0, 2 and of 4 at 5 -> 37, f1 spans (0, 6) -> bits of 6 at 3, 5 -> 40;
+    f3 crosses nothing and ranks last.  (The mean position would put f1, 3.0, ahead
+    of f0, 3.5.)"""
+    fascicle = np.array([0, 0, 1, 1, 2], np.int32)
+    voxel = np.array([3, 4, 0, 6, 1], np.int32)
+    p = life.plan_host(2, 1, 8, 4, np.zeros(5, np.int16), voxel, fascicle)
+    assert np.array_equal(p["fas_rank"], [1, 2, 0, 3])
+    from conftest import fascicle_keys
+    assert np.array_equal(fascicle_keys(fascicle, voxel, 4)[:3], [74, 80, 6])
+
+
 def test_negative_coordinate_rejected():
     c = connectome("tiny")
     xyz = c.voxel_xyz.copy()
@@ -141,22 +155,20 @@ def _batch_instances():
 
 def _reference_batch_plan(inst):
     """Batched restructuring computed independently: positions instance by instance
-    (Morton inside, blocks padded to 64), ranks by mean position (empty fascicles at
+    (Morton inside, blocks padded to 64), ranks by fascicle_keys (empty fascicles at
     the end of their instance), then the same lexsorts as reference_plan."""
-    from conftest import morton_positions
+    from conftest import fascicle_keys, morton_positions
     dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = life.concat_instances(inst)
     pp = np.empty(dims.n_voxels, np.int64)
-    empty_key = np.empty(dims.n_fascicles)
+    empty_end = np.empty(dims.n_fascicles, np.int64)
     base = 0
     for k in range(len(inst)):
         v0, v1 = vox_off[k], vox_off[k + 1]
         pp[v0:v1] = base + morton_positions(xyz[v0:v1])
         base += -(-(v1 - v0) // 64) * 64
-        empty_key[fas_off[k]:fas_off[k + 1]] = base
+        empty_end[fas_off[k]:fas_off[k + 1]] = base
     pos = np.arange(dims.nnz)
-    cnt = np.bincount(fascicle, minlength=dims.n_fascicles)
-    tot = np.bincount(fascicle, weights=pp[voxel].astype(np.float64), minlength=dims.n_fascicles)
-    key = np.where(cnt > 0, tot / np.maximum(cnt, 1), empty_key)
+    key = fascicle_keys(fascicle, pp[voxel], dims.n_fascicles, empty_end)
     order = np.argsort(key, kind="stable")
     rank = np.empty(dims.n_fascicles, np.int64)
     rank[order] = np.arange(dims.n_fascicles)
