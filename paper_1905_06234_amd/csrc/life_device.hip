@@ -407,25 +407,30 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
     }
 }
 
-// WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every entry q of the
-// chunked layout (pad entries give 0).  z_pos keeps each chunk's values inside the
-// chunk's own range, grouped by tile and in WC order inside a tile, so pass 2 reads
-// one fascicle's values in a chunk as short contiguous runs.
+// WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every real entry q of
+// the chunked layout (pads are skipped: pass 2 never reads them).  z_pos keeps each
+// chunk's values inside the chunk's own range, grouped by tile and in WC order
+// inside a tile, so pass 2 reads one fascicle's values in a chunk as short
+// contiguous runs, and one tile's values fill the sub-range
+// [tile_z[2 i], tile_z[2 i] + tile_z[2 i + 1]) of i = chunk T + t.
 // LDS: P [32 AB][kPS] floats, Y hi and lo [64 slots][YS] halves (YS = 16 KS + 8:
-// conflict-free 16-byte reads along theta), the 64 slot scales.  Waves 0..AB-1
-// each form one 32-atom block of P for both 32-slot halves; then every wave looks
-// up its own slots' nonzeros.
+// conflict-free 16-byte reads along theta), the 64 slot scales, then cap floats
+// that stage the first cap values of the tile's sub-range.  Waves 0..AB-1 each form
+// one 32-atom block of P for both 32-slot halves; then every wave looks up its own
+// slots' nonzeros and puts each value in the stage (or, beyond cap, straight into
+// z); the stage then goes out as one coalesced stream.
 __global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ chunk_map,
                                                   const int32_t *__restrict__ chunk_vox,
                                                   const int32_t *__restrict__ wave_work,
                                                   const int16_t *__restrict__ atom,
                                                   const float *__restrict__ phi,
                                                   const int32_t *__restrict__ z_pos,
+                                                  const int32_t *__restrict__ tile_z,
                                                   const h8 *__restrict__ frag,
                                                   const float *__restrict__ dscale,
                                                   const float *__restrict__ y,
                                                   float *__restrict__ z, int nth, int T, int TA, int AB,
-                                                  int KS, Gate gate)
+                                                  int KS, int cap, Gate gate)
 {
     if (gated_off(gate)) return;   // uniform over the grid
     extern __shared__ float4 lds4[];
@@ -434,6 +439,7 @@ __global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ ch
     _Float16 *Yh = reinterpret_cast<_Float16 *>(P + AB * 32 * kPS);
     _Float16 *Yl = Yh + kChunkVoxels * YS;
     float *yscale = reinterpret_cast<float *>(Yl + kChunkVoxels * YS);
+    float *stage = yscale + kChunkVoxels;
     const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -496,6 +502,7 @@ __global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ ch
         __syncthreads();
         const WaveRange R(wave_work, chunk, t, T, wave);
         const int p1 = R.p[1], p2 = R.p[2], p3 = R.p[3], pe = R.p[kWaveVoxels];
+        const int zbeg = uni(tile_z[2 * (chunk * T + t)]), zcnt = uni(tile_z[2 * (chunk * T + t) + 1]);
         for (int b = R.p[0]; b < pe; b += 4 * 64) {
             int aa[4], zz[4];
             float ff[4];
@@ -510,12 +517,18 @@ __global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ ch
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = b + 64 * u + lane;
-                if (idx < pe) {
+                const int loc = zz[u] - zbeg;
+                if (idx < pe && (unsigned)loc < (unsigned)zcnt) {
                     const int slot = wave * kWaveVoxels + (idx >= p1) + (idx >= p2) + (idx >= p3);
-                    z[zz[u]] = ff[u] * P[(aa[u] - a0) * kPS + slot];
+                    const float v = ff[u] * P[(aa[u] - a0) * kPS + slot];
+                    if (loc < cap) stage[loc] = v;
+                    else z[zz[u]] = v;
                 }
             }
         }
+        __syncthreads();   // the stage is complete (the next tile's first barrier guards its reuse)
+        const int n = min(zcnt, cap);
+        for (int i = threadIdx.x; i < n; i += kWG) z[zbeg + i] = stage[i];
     }
 }
 
@@ -1038,8 +1051,10 @@ struct life_plan_s {
     float *phi_c = nullptr;       // [n_pad]
     int32_t *z_pos = nullptr;     // [n_pad] z position of each padded entry
     int32_t *wc_perm_z = nullptr; // [nnz] z position of each WC slot
+    int32_t *tile_z = nullptr;    // [n_chunks * n_tiles * 2] first z position and count per (chunk, tile)
     // WC pass 1 on the matrix cores: split D^T operands (k_split_dt) and the LDS size
     int dt_ab = 0, dt_ks = 0;     // atom blocks of 32 per tile, k-steps of 16 theta
+    int wcz_cap = 0;              // floats of LDS that stage a tile's z values (0: none)
     size_t wcz_lds = 0;
     h8 *dt_frag = nullptr;        // [n_tiles][dt_ab][dt_ks][2][64]
     float *dt_scale = nullptr;    // [n_tiles][dt_ab][32]
@@ -1100,7 +1115,7 @@ hipError_t dalloc(T **p, int64_t n)
 void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c, p->fas_c,
-                    p->phi_c, p->z_pos, p->wc_perm_z, p->dt_frag, p->dt_scale, p->fas_rank, p->fas_ext,
+                    p->phi_c, p->z_pos, p->wc_perm_z, p->tile_z, p->dt_frag, p->dt_scale, p->fas_rank, p->fas_ext,
                     p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
                     p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
@@ -1251,8 +1266,9 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
                                                                                          nth, p->dims.n_atoms, T, TA,
                                                                                          AB, KS, gate);
                 k_wcz_mfma<<<p->chunk_grid, kWG, p->wcz_lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work, p->atom_c,
-                                                                  p->phi_c, p->z_pos, p->dt_frag, p->dt_scale, y, p->z,
-                                                                  nth, T, TA, AB, KS, gate);
+                                                                  p->phi_c, p->z_pos, p->tile_z, p->dt_frag,
+                                                                  p->dt_scale, y, p->z, nth, T, TA, AB, KS,
+                                                                  p->wcz_cap, gate);
             });
         } else {
             const int grid = cdiv(nv, kSegPerBlock);
@@ -1338,7 +1354,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         vox_off = one_v;
         fas_off = one_f;
     }
-    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, ppos, pvox, vdsc;
+    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, tilez, ppos, pvox, vdsc;
     std::vector<int32_t> aptr, avox, afas, cmap;
     std::vector<int64_t> chunk_work;
     std::vector<float> aphi;
@@ -1417,7 +1433,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), pvox.data(), n_pos, tptr.data(), cvox.data());
             n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), ppos.data(), atom_v.data(),
                                          fas_v.data(), phi_v.data(), vdsc.data(), wperm.data(), wwork, atom_c,
-                                         fas_c, phi_c, zpos, wperm_z);
+                                         fas_c, phi_c, zpos, wperm_z, tilez);
             if (n_pad < 0) return LIFE_ERANGE;
             std::vector<int64_t> work((size_t)n_chunks);
             const size_t per_chunk = (size_t)tg.n_tiles * kChunkWaves * life::kWorkInts;
@@ -1467,6 +1483,9 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             delete p;
             return LIFE_EINVAL;   // cannot happen: tiles hold at most kMaxTileAtoms atoms, N_theta <= 128
         }
+        // the rest of the LDS budget stages z (whole 16-byte units)
+        p->wcz_cap = (int)(((size_t)life::kLdsBudget - p->wcz_lds) / 16 * 4);
+        p->wcz_lds += (size_t)p->wcz_cap * sizeof(float);
     }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -1482,6 +1501,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     chk(dalloc(&p->phi_c, n_pad));
     chk(dalloc(&p->z_pos, (int64_t)zpos.size()));
     chk(dalloc(&p->wc_perm_z, (int64_t)wperm_z.size()));
+    chk(dalloc(&p->tile_z, (int64_t)tilez.size()));
     if (n_chunks > 0) {
         chk(dalloc(&p->dt_frag, (int64_t)tg.n_tiles * p->dt_ab * p->dt_ks * 2 * 64));
         chk(dalloc(&p->dt_scale, (int64_t)tg.n_tiles * p->dt_ab * 32));
@@ -1527,6 +1547,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     up(p->phi_c, phi_c.data(), sizeof(float) * phi_c.size());
     up(p->z_pos, zpos.data(), sizeof(int32_t) * zpos.size());
     up(p->wc_perm_z, wperm_z.data(), sizeof(int32_t) * wperm_z.size());
+    up(p->tile_z, tilez.data(), sizeof(int32_t) * tilez.size());
     up(p->fas_rank, rank.data(), sizeof(int32_t) * rank.size());
     up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());

@@ -109,13 +109,14 @@ std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePo
 // entries tile by tile, in WC order inside a tile (so one fascicle's entries of
 // one tile in one chunk are adjacent, and the writes of one tile's pass stay in
 // one sub-range), then its pad entries.  z_pos[q] = z position of padded entry q;
-// wc_perm_z[j] = z position of WC slot j.  Returns the padded length, or -1 if it
-// exceeds the 32-bit position limit.
+// wc_perm_z[j] = z position of WC slot j; tile_z[2 (c T + t)] and [.. + 1] = first
+// z position and number of the (real) entries of chunk c in tile t.  Returns the
+// padded length, or -1 if it exceeds the 32-bit position limit.
 int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
                        const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
                        const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
                        const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
                        std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
-                       std::vector<int32_t> &wc_perm_z);
+                       std::vector<int32_t> &wc_perm_z, std::vector<int32_t> &tile_z);
 
 }  // namespace life

@@ -368,7 +368,7 @@ int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, con
                        const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
                        const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
                        std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
-                       std::vector<int32_t> &wc_perm_z)
+                       std::vector<int32_t> &wc_perm_z, std::vector<int32_t> &tile_z)
 {
     const int T = tg.n_tiles;
     wave_work.assign((size_t)n_chunks * T * kChunkWaves * kWorkInts, 0);
@@ -409,11 +409,14 @@ int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, con
         const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
         tnext[(size_t)c * T + atom_v[p] / tg.tile_atoms]++;
     }
+    tile_z.assign((size_t)n_chunks * T * 2, 0);
     for (int c = 0; c < n_chunks; ++c) {
         int64_t b = next[c];
         for (int t = 0; t < T; ++t) {
             const int64_t n = tnext[(size_t)c * T + t];
             tnext[(size_t)c * T + t] = b;
+            tile_z[2 * ((size_t)c * T + t)] = static_cast<int32_t>(b);
+            tile_z[2 * ((size_t)c * T + t) + 1] = static_cast<int32_t>(n);
             b += n;
         }
         next[c] = b;   // pads follow the real entries
