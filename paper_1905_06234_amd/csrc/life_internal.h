@@ -54,6 +54,9 @@ constexpr int kWaveVoxels = 4;
 constexpr int kChunkVoxels = kChunkWaves * kWaveVoxels;
 constexpr int kMaxTileRowFloats = 128;      // chunked kernels handle n_theta <= 128
 constexpr int kLdsBudget = 160 * 1024 - 1024;
+// A staged dictionary tile takes at most half of a CU's LDS, so that two DSC
+// workgroups (64 VGPRs per lane: 8 waves per SIMD) share a CU.
+constexpr int kTileBytes = 80 * 1024;
 // Dictionary-gradient kernel: per tile, a dense (atom x voxel slot) block of the
 // chunk and the chunk's (theta x voxel slot) signal block in LDS, rows of
 // kPsiStride floats (64 slots + 4 to spread the banks); a tile has at most

@@ -252,7 +252,7 @@ TileGeom tile_geometry(int n_theta, int n_atoms)
     TileGeom g;
     const int row = ((n_theta + 31) / 32) * 32;
     if (row > kMaxTileRowFloats) return g;
-    const int max_atoms = std::min(kLdsBudget / (row * 4), kMaxTileAtoms);
+    const int max_atoms = std::min(kTileBytes / (row * 4), kMaxTileAtoms);
     const int n_tiles = (n_atoms + max_atoms - 1) / max_atoms;
     g.row_floats = row;
     g.n_tiles = n_tiles;
