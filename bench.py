@@ -174,6 +174,37 @@ def algorithmic(kind: str, d) -> tuple[float, float]:
     return 0.0, 0.0
 
 
+def pair_bytes(d) -> float:
+    """Algorithmic bytes of one DSC plus one WC: the sorted streams, each dense vector
+    once, D once."""
+    nnz, nt, nv, nf, na = d.nnz, d.n_theta, d.n_voxels, d.n_fascicles, d.n_atoms
+    b_dsc = 10.0 * nnz + 4.0 * nt * nv + 4.0 * nf + 4.0 * nt * na + 4.0 * (nv + 1)
+    b_wc = 10.0 * nnz + 4.0 * nt * nv + 4.0 * nf + 4.0 * nt * na + 4.0 * (nf + 1)
+    return b_dsc + b_wc
+
+
+def cold_mall_kernels(plan, D, b, w, state, steps: int) -> dict:
+    """Per-kernel times of SBB steps with a 512 MB device copy between steps, so each
+    step starts with the Infinity Cache (256 MB) holding none of its data.  Only the
+    library's own launches are timed (the copy is outside their events)."""
+    import torch
+    src = torch.empty(64 << 20, dtype=torch.float32, device=D.device)
+    dst = torch.empty_like(src)
+    plan.profile_read()
+    for _ in range(steps):
+        dst.copy_(src)
+        plan.profile_enable(True)
+        plan.sbbnnls_step(D, b, w, state)
+        plan.profile_enable(False)
+    torch.cuda.synchronize()
+    ms, cnt = plan.profile_read()
+    del src, dst
+    avg = {k: (ms[k] / cnt[k] if cnt[k] else 0.0) for k in ms}
+    t = avg["dsc"] + avg["wc_z"] + avg["wc_sum"]
+    return {"kernel_avg_ms": {k: round(v, 4) for k, v in avg.items() if cnt[k]},
+            "pair_kernel_nnz_per_s": round(plan.dims.nnz / (t / 1e3), 1) if t > 0 else None, "steps": steps}
+
+
 def cpu_baseline(c, target_s: float):
     """FP64 oracle DSC + WC on a random sample of the nonzeros (bounded time)."""
     import numpy as np
@@ -352,6 +383,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--voxel-order", default="morton", choices=["morton", "index"],
                     help="voxel processing order of the plan: Morton order of the grid coordinates, or voxel index")
+    ap.add_argument("--mall-flush", action="store_true",
+                    help="also time the kernels with a 512 MB copy between steps (cold Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="sbb", choices=["sbb", "adam", "batched"],
@@ -484,11 +517,17 @@ def main():
                    "voxel_order": args.voxel_order,
                    "step": "one SBB-NNLS iteration (2 DSC + 1 or 2 WC + glue)"},
         "pair_kernel_nnz_per_s": round(d.nnz / ((t_dsc + t_wc) / 1e3), 1) if t_dsc + t_wc > 0 else None,
+        # algorithmic bytes of one DSC plus one WC over their kernel times, against 8 TB/s
+        "pair_hbm_frac": round(pair_bytes(d) / ((t_dsc + t_wc) / 1e3) / (HBM_PEAK_GBS * 1e9), 4)
+        if t_dsc + t_wc > 0 else None,
         "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},
         "kernel_launches": cnt,
         "plan_ms": round(plan_ms, 1),
         "roofline": roof,
     }
+    if args.mall_flush:
+        out["cold_mall"] = cold_mall_kernels(plan, D, b, w, state, args.steps)
+        log(f"cold-MALL kernel times: {out['cold_mall']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
