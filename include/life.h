@@ -215,6 +215,11 @@ life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y,
  * phi_c * sum_t D[t + N_theta*atom_c] * y[t + N_theta*voxel_c].
  *   D (device), y (device, N_theta*N_v) are read; g (device, N_f) is
  *   overwritten (fascicles with no nonzero get 0).
+ * Precision: with N_theta <= 128 the inner products <D[:,a], y[:,v]> are formed
+ *   on the matrix cores from FP16 hi/lo pairs of power-of-two scaled columns of D
+ *   and y (about 22 significant bits per operand, FP32 accumulation; relative
+ *   error per product about 3 * 2^-22 against 2^-24 for an FP32 FMA); the sums
+ *   over nonzeros are FP32 in a fixed order.  Larger N_theta uses FP32 FMAs.
  * Errors: as life_dsc. */
 life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream);
 

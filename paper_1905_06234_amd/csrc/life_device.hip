@@ -4,8 +4,7 @@
 //      over the voxel-sorted nonzeros; every y column is accumulated in
 //      registers and written exactly once (no atomics).
 // WC   g = M^T y  (the transpose product of eq. 6), in two deterministic passes:
-//      (1) voxel-major: a voxel's signal column stays in registers while each of
-//          its nonzeros c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
+//      (1) voxel-major: each nonzero c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
 //      (2) fascicle-major: g[f] = sum of z over the fascicle's nonzeros, read
 //          through the fascicle-sorted permutation, in a fixed tree order.
 // SBB  one SBB-NNLS iteration (Algorithm 1) chains these with a mask kernel, a
@@ -13,15 +12,20 @@
 //      the device and every reduction has a fixed order.
 //
 // Two implementations of DSC and WC pass 1 exist:
-//   chunked (n_theta <= 128): a 1024-thread workgroup owns 64 voxels; the
-//     dictionary is staged in LDS one atom tile at a time (3 tiles of 353 atoms
-//     for N_theta = 96, 135.5 KB); inside a wave, four 16-lane groups each take
-//     one nonzero per step, lane l of a group holding theta = 32c + 2l, 2l + 1, so
-//     a step is 3 ds_read_b64 + 6 FMA per lane.  The per-nonzero scalars are
-//     loaded coalesced once per 64 nonzeros and broadcast inside each group with
-//     a DPP row broadcast (a VALU move, leaving the LDS pipe to the D reads).  This replaces the paper's one-warp-per-sub-vector mapping,
-//     which on a 64-wide wavefront with N_theta = 96 would idle lanes and read D
-//     through the cache hierarchy at 384 B per nonzero.
+//   chunked (n_theta <= 128): a 1024-thread workgroup owns 64 voxels and works
+//     one atom tile at a time (a tile of D takes at most 80 KB: 5 tiles of 212
+//     atoms for N_theta = 96, so two DSC workgroups share a CU).
+//     DSC stages the tile in LDS; inside a wave, four 16-lane groups each take one
+//     nonzero per step, lane l of a group holding theta = 32c + 2l, 2l + 1, so a
+//     step is 3 ds_read_b64 + 6 FMA per lane.  The per-nonzero scalars are loaded
+//     coalesced once per 64 nonzeros and broadcast inside each group with a DPP
+//     row broadcast (a VALU move, leaving the LDS pipe to the D reads).  This
+//     replaces the paper's one-warp-per-sub-vector mapping, which on a 64-wide
+//     wavefront with N_theta = 96 would idle lanes and read D through the cache
+//     hierarchy at 384 B per nonzero.
+//     WC pass 1 forms all the tile's projections of the chunk at once, as the
+//     dense block D_tile^T Y_chunk on the matrix cores (split-FP16 operands),
+//     then each nonzero is one lookup; its z values leave through an LDS stage.
 //   generic (any n_theta <= 1024): 32 lanes per voxel, D read through L1/L2.
 #include <hip/hip_runtime.h>
 
