@@ -35,20 +35,30 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector; a plain v_fma_f32 loop re
 
 # rocprofv3 commands whose outputs --summarize reads (run from /tmp with
 # TMPDIR=/tmp; the synthetic connectome cached through LIFE_SYNTH_CACHE)
-PROFILE_COMMANDS = {
-    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof/trace -o run -- "
-             "python3 $R/bench.py --steps 6 --warmup 2 --no-cpu-baseline",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/fetch -o run -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/write -o run -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "tcc": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d $R/gpurun_out/prof/tcc -o run -- "
-           "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-    "copyf": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof/copyf -o run -- "
-             "python3 $R/bench.py --copy-probe",
-    "copyw": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof/copyw -o run -- "
-             "python3 $R/bench.py --copy-probe",
-}
+def profile_commands(config: str) -> dict:
+    """The rocprofv3 runs behind profiles/<config>_*: a kernel trace, then FETCH_SIZE,
+    WRITE_SIZE and the L2 hit counters in runs of their own, and the copy probe that
+    calibrates the byte counters."""
+    cfg = "" if config == "full" else f" --config {config}"
+    out = "$R/gpurun_out/prof" + ("" if config == "full" else f"_{config}")
+    run = f"python3 $R/bench.py{cfg}"
+    return {
+        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/trace -o run -- "
+                 f"{run} --steps 6 --warmup 2 --no-cpu-baseline",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/fetch -o run -- "
+                 f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/write -o run -- "
+                 f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
+        "tcc": f"rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d {out}/tcc -o run -- "
+               f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
+        "copyf": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/copyf -o run -- "
+                 "python3 $R/bench.py --copy-probe",
+        "copyw": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/copyw -o run -- "
+                 "python3 $R/bench.py --copy-probe",
+    }
+
+
+PROFILE_COMMANDS = profile_commands("full")
 KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_mfma", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
 # profiling classes launched by the same kernel (the second WC of even iterations)
 KIND_GROUPS = {"dsc": ("dsc",), "wc_z": ("wc_z", "wc_z_2nd"), "wc_sum": ("wc_sum", "wc_sum_2nd")}
@@ -119,7 +129,7 @@ def summarize(prof_dir: str, workload: str):
     rec = {"workload": workload, "source_sha256": source_hash(),
            "copy_probe": {"bytes_each_way": copy_bytes, "fetch_kib": ckf, "write_kib": ckw,
                           "fetch_factor": ff, "write_factor": fw},
-           "kernels": kernels, "commands": PROFILE_COMMANDS}
+           "kernels": kernels, "commands": profile_commands(workload)}
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, f"{workload}_counters.json"), "w") as fh:
@@ -137,8 +147,10 @@ def summarize(prof_dir: str, workload: str):
                      f"{e.get('write_kib', '-')} | {gb} | {e.get('l2_hit_rate', '-')} |")
     lines += ["", f"Library source SHA-256: `{rec['source_sha256']}`", "",
               "Commands (repository root `$R`; run from `/tmp` with `TMPDIR=/tmp`,",
-              "`LIFE_SYNTH_CACHE=/tmp/life_synth`), then `python3 bench.py --summarize $R/gpurun_out/prof`:", ""]
-    lines += [f"    {c}" for c in PROFILE_COMMANDS.values()]
+              "`LIFE_SYNTH_CACHE=/tmp/life_synth`), then "
+              f"`python3 bench.py{'' if workload == 'full' else ' --config ' + workload} --summarize "
+              f"$R/gpurun_out/prof{'' if workload == 'full' else '_' + workload}`:", ""]
+    lines += [f"    {c}" for c in profile_commands(workload).values()]
     with open(os.path.join(out_dir, f"{workload}_kernels.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps({"summarized": workload, "kernels": list(kernels)}))
