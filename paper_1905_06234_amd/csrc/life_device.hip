@@ -694,9 +694,12 @@ constexpr int kPsiStride = life::kPsiStride;
 // dD_tile += Ybar_chunk * Psi^T is a dense product over the chunk's 64 voxel slots
 // on the matrix cores (v_mfma_f32_16x16x4_f32, FP32 in, FP32 accumulate), with
 // Ybar_chunk staged in LDS as [theta][slot].
-// One workgroup owns one atom tile and one contiguous group of chunks; it keeps
-// its dD_tile share in the accumulators and writes it once to part (layout
-// [tile][group][atom of tile][theta, padded to 16]); k_dd_reduce sums the groups.
+// One workgroup owns one span of S consecutive atom tiles of the plan (a "dd
+// tile" of up to S TA atoms: fewer, larger blocks than the DSC tiles, so the
+// chunk's Ybar staging and the block's zeroing are shared by S tiles) and one
+// contiguous group of chunks; it keeps its share of dD in the accumulators and
+// writes it once to part (layout [dd tile][group][atom of dd tile][theta, padded
+// to 16]); k_dd_reduce sums the groups.
 //   MFMA operands (16 x 16 x 4 per instruction, 16 steps per chunk): lane l has
 //   row = l % 16, kq = l / 16; at step s the reduction index kq stands for voxel
 //   slot 16 kq + s, so the 16 steps cover the 64 slots once:
@@ -712,7 +715,7 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
                                                   const float *__restrict__ w,
                                                   const float *__restrict__ ybar,
                                                   float *__restrict__ part, int nth, int T, int TA, int TAP,
-                                                  int n_chunks, int G)
+                                                  int S, int n_chunks, int G)
 {
     extern __shared__ float4 lds4[];
     float *psi = reinterpret_cast<float *>(lds4);
@@ -720,9 +723,10 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
     float *ylds = psi + TAP * kPsiStride;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int item = xcd_item();
-    const int t = item % T, grp = item / T;
+    const int DT = (T + S - 1) / S;
+    const int u = item % DT, grp = item / DT;
     const int c0 = (int)((int64_t)grp * n_chunks / G), c1 = (int)((int64_t)(grp + 1) * n_chunks / G);
-    const int a0 = t * TA;
+    const int a0 = u * S * TA, t_end = min(T, (u + 1) * S);
     const int MB = TAP / 16, NB = NTB * MB;
     const int b_lo = wave * NB / kChunkWaves, b_hi = (wave + 1) * NB / kChunkWaves;   // this wave's blocks
     const int row = lane & 15, kq = lane >> 4;
@@ -740,28 +744,44 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
             ylds[th * kPsiStride + slot] = (v >= 0 && th < nth) ? ybar[(size_t)v * nth + th] : 0.f;
         }
         __syncthreads();
-        // Psi of this chunk and tile: one nonzero per lane; atoms never decrease inside
-        // a slot's sub-range, so equal atoms form runs, summed by a segmented scan
-        {
+        // Psi of this chunk and dd tile: one nonzero per lane, four batches of 64 in
+        // flight over the wave's whole range (its 4 slots in turn); atoms never
+        // decrease inside a slot's sub-range, so runs of equal (slot, atom) are summed
+        // by a segmented scan
+        for (int t = u * S; t < t_end; ++t) {
             const WaveRange R(wave_work, c, t, T, wave);
+            const int p1 = R.p[1], p2 = R.p[2], p3 = R.p[3], pe = R.p[kWaveVoxels];
+            for (int b = R.p[0]; b < pe; b += 4 * 64) {
+                int aa[4], ff[4];
+                float ph[4], sv[4];
 #pragma unroll
-            for (int j = 0; j < kWaveVoxels; ++j) {
-                float *col = psi + wave * kWaveVoxels + j;
-                for (int b = R.p[j]; b < R.p[j + 1]; b += 64) {
-                    const int m = min(64, R.p[j + 1] - b);
-                    const bool valid = lane < m;
-                    const int q = valid ? b + lane : b;
-                    const int a = atom[q];
-                    float sv = valid ? phi[q] * w[fas[q]] : 0.f;
-                    const int key = valid ? a : -1;
+                for (int h = 0; h < 4; ++h) {
+                    const int idx = b + 64 * h + lane;
+                    const int ix = idx < pe ? idx : R.p[0];
+                    aa[h] = atom[ix];
+                    ff[h] = fas[ix];
+                    ph[h] = phi[ix];
+                }
 #pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const float so = __shfl_up(sv, o, 64);
-                        const int ko = __shfl_up(key, o, 64);
-                        if (lane >= o && ko == key) sv += so;
+                for (int h = 0; h < 4; ++h) sv[h] = ph[h] * w[ff[h]];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int idx = b + 64 * h + lane;
+                    if (b + 64 * h < pe) {   // uniform
+                        const bool valid = idx < pe;
+                        const int j = (idx >= p1) + (idx >= p2) + (idx >= p3);
+                        const int key = valid ? (j << 16) | aa[h] : -1;
+                        float v = valid ? sv[h] : 0.f;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const float vo = __shfl_up(v, o, 64);
+                            const int ko = __shfl_up(key, o, 64);
+                            if (lane >= o && ko == key) v += vo;
+                        }
+                        const int kn = __shfl_down(key, 1, 64);
+                        if (valid && (lane == 63 || kn != key))
+                            psi[(aa[h] - a0) * kPsiStride + wave * kWaveVoxels + j] += v;
                     }
-                    const int kn = __shfl_down(key, 1, 64);
-                    if (valid && (lane == 63 || kn != key)) col[(a - a0) * kPsiStride] += sv;
                 }
             }
         }
@@ -784,7 +804,7 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
             }
         }
     }
-    float *out = part + (size_t)(t * G + grp) * TAP * NT16;
+    float *out = part + (size_t)(u * G + grp) * TAP * NT16;
 #pragma unroll
     for (int k = 0; k < NBW; ++k) {
         const int bb = b_lo + k;
@@ -1076,7 +1096,7 @@ struct life_plan_s {
     double *part = nullptr;       // 5 regions of part_stride
     int64_t part_stride = 0;
     // dictionary gradient: chunked (per tile and chunk group partials) ...
-    int dd_groups = 0, dd_tap = 0, dd_nbw = 0;
+    int dd_groups = 0, dd_tap = 0, dd_nbw = 0, dd_span = 1;   // dd tile = dd_span plan tiles
     float *dd_part = nullptr;     // [T][groups][dd_tap][16 ceil(Nt/16)]
     // ... or generic (atom-major copy of the nonzeros)
     int32_t *a_ptr = nullptr;     // [Na + 1]
@@ -1309,15 +1329,18 @@ life_status enqueue_dd(life_plan_s *p, const float *ybar, float *dD, hipStream_t
     const int nth = d.n_theta, na = d.n_atoms;
     if (chunked(p)) {
         const int T = p->tile.n_tiles, TA = p->tile.tile_atoms, TAP = p->dd_tap, G = p->dd_groups;
+        const int S = p->dd_span, DT = (T + S - 1) / S;
         const size_t lds = (size_t)(TAP + (nth + 15) / 16 * 16) * kPsiStride * sizeof(float);
         life_status st = launch(p, LIFE_K_DD, s, [&] {
-            LIFE_DISPATCH_NBW(p->dd_nbw, k_dd_chunk, T * G, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
-                                                                         p->fas_c, p->phi_c, p->w_rank, ybar,
-                                                                         p->dd_part, nth, T, TA, TAP, p->n_chunks, G))
+            LIFE_DISPATCH_NBW(p->dd_nbw, k_dd_chunk, DT * G, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
+                                                                          p->fas_c, p->phi_c, p->w_rank, ybar,
+                                                                          p->dd_part, nth, T, TA, TAP, S,
+                                                                          p->n_chunks, G))
         });
         if (st != LIFE_OK) return st;
+        // a dd tile holds S TA atoms
         return launch(p, LIFE_K_DD_REDUCE, s, [&] {
-            k_dd_reduce<<<cdiv((int64_t)na * nth, kBlock), kBlock, 0, s>>>(p->dd_part, dD, nth, na, TA, TAP, G);
+            k_dd_reduce<<<cdiv((int64_t)na * nth, kBlock), kBlock, 0, s>>>(p->dd_part, dD, nth, na, S * TA, TAP, G);
         });
     }
     return launch(p, LIFE_K_DD, s, [&] {
@@ -1472,11 +1495,23 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     int64_t dd_floats = 0;
     if (n_chunks > 0) {
         const int T = tg.n_tiles;
-        p->dd_tap = (tg.tile_atoms + 15) / 16 * 16;
-        p->dd_groups = std::max(1, std::min(n_chunks, 512 / T));
-        const int nb_blocks = (d.n_theta + 15) / 16 * (p->dd_tap / 16);
+        // the widest span of tiles whose block fits the LDS and the accumulator variants
+        const int nt16 = (d.n_theta + 15) / 16 * 16;
+        p->dd_span = 1;
+        for (int sp = 2; sp <= T; ++sp) {
+            const int tap = (sp * tg.tile_atoms + 15) / 16 * 16;
+            const int blocks = nt16 / 16 * (tap / 16);
+            if (sp * tg.tile_atoms > life::kMaxTileAtoms || (int64_t)(tap + nt16) * kPsiStride * 4 > life::kLdsBudget ||
+                dd_nbw_variant((blocks + kChunkWaves - 1) / kChunkWaves) < 0)
+                break;
+            p->dd_span = sp;
+        }
+        const int DT = (T + p->dd_span - 1) / p->dd_span;
+        p->dd_tap = (p->dd_span * tg.tile_atoms + 15) / 16 * 16;
+        p->dd_groups = std::max(1, std::min(n_chunks, 512 / DT));
+        const int nb_blocks = nt16 / 16 * (p->dd_tap / 16);
         p->dd_nbw = dd_nbw_variant((nb_blocks + kChunkWaves - 1) / kChunkWaves);
-        dd_floats = (int64_t)T * p->dd_groups * p->dd_tap * ((d.n_theta + 15) / 16 * 16);
+        dd_floats = (int64_t)DT * p->dd_groups * p->dd_tap * nt16;
         p->dt_ab = (tg.tile_atoms + 31) / 32;
         p->dt_ks = (d.n_theta + 15) / 16;
         p->wcz_lds = (size_t)p->dt_ab * 32 * kPS * sizeof(float) +
