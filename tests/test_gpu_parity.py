@@ -34,6 +34,9 @@ RANDOM_SHAPES = {
     # (~19k values at N_theta = 96, ~5k at 16), so part of z bypasses the stage
     "dense96": (96, 200, 64, 5000, 30_000, True),
     "dense16": (16, 512, 64, 3000, 20_000, False),
+    # one chunk over 5 atom tiles with twice the stage's capacity: the overflow part of
+    # z is grouped by tile
+    "dense96t": (96, 1057, 64, 8000, 40_000, False),
 }
 
 
