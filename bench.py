@@ -158,7 +158,8 @@ def summarize(prof_dir: str, workload: str):
 
 def recorded_traffic(workload: str, kind: str):
     """HBM bytes per launch of the kernel class from profiles/, or None when the
-    record is missing or was taken on other library sources."""
+    record is missing or was taken on other library sources (the records are taken
+    with the default Morton voxel order)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -514,7 +515,7 @@ def main():
     t_copy = _time_ms(lambda: dst.copy_(src), 5)
     copy_gbs = 2.0 * src.numel() * 4 / (t_copy / 1e3) / 1e9
     del src, dst
-    roof.update({"traffic": recorded_traffic(args.config, dom), "kernel": dom, "avg_ms": round(dom_ms, 4),
+    roof.update({"traffic": recorded_traffic(args.config, dom) if args.voxel_order == "morton" else None, "kernel": dom, "avg_ms": round(dom_ms, 4),
                  "achievable_copy_GBs": round(copy_gbs, 1),
                  "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
                  "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})
