@@ -515,7 +515,8 @@ def main():
     t_copy = _time_ms(lambda: dst.copy_(src), 5)
     copy_gbs = 2.0 * src.numel() * 4 / (t_copy / 1e3) / 1e9
     del src, dst
-    roof.update({"traffic": recorded_traffic(args.config, dom) if args.voxel_order == "morton" else None, "kernel": dom, "avg_ms": round(dom_ms, 4),
+    traffic = recorded_traffic(args.config, dom) if args.voxel_order == "morton" else None
+    roof.update({"traffic": traffic, "kernel": dom, "avg_ms": round(dom_ms, 4),
                  "achievable_copy_GBs": round(copy_gbs, 1),
                  "algorithmic_bytes": int(by), "algorithmic_flops": int(fl),
                  "hbm_GBs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)})
