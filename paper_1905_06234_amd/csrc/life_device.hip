@@ -95,9 +95,17 @@ __device__ __forceinline__ void block_sum_store(double v, double *out, int slot)
 __device__ double block_sum_array(const double *a, int n)
 {
     __shared__ double sh[kAlphaThreads];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kAlphaThreads) s += a[i];
-    sh[threadIdx.x] = s;
+    // four independent running sums per thread (four loads in flight), combined in a fixed order
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * kAlphaThreads < n; i += 4 * kAlphaThreads) {
+        s0 += a[i];
+        s1 += a[i + kAlphaThreads];
+        s2 += a[i + 2 * kAlphaThreads];
+        s3 += a[i + 3 * kAlphaThreads];
+    }
+    for (; i < n; i += kAlphaThreads) s0 += a[i];
+    sh[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     for (int w = kAlphaThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
