@@ -254,6 +254,55 @@ def _time_ms(fn, reps: int) -> float:
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+def bench_solve(args):
+    """A whole SBB-NNLS solve: --iterations iterations (default 500, the paper's run
+    length) from w0 on the chosen connectome, timed end to end on the device, with
+    the objective read back after the first iteration and every 50 (outside the
+    timed stretches); the state after iteration i holds f(w) = 1/2 ||M w - b||^2 at
+    the iterate that iteration started from."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_06234_amd import life
+
+    life.load()
+    dev = torch.device("cuda:0")
+    c = synth.make(args.config)
+    plan = life.Plan.from_connectome(c, morton=args.voxel_order == "morton")
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    y_true = plan.dsc(D, torch.from_numpy(c.w_true).to(dev))
+    rms = torch.sqrt(torch.mean(y_true.double() ** 2)).float()
+    b = y_true + 0.05 * rms * torch.from_numpy(c.noise).to(dev)
+    del y_true
+    w = torch.from_numpy(c.w0).to(dev)
+    state = life.new_state(dev)
+    torch.cuda.synchronize()
+    trace, elapsed, done = [], 0.0, 0
+    while done < args.iterations:
+        k = min(1 if done == 0 else 50 - done % 50, args.iterations - done)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            plan.sbbnnls_step(D, b, w, state)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        done += k
+        st = life.read_state(state)
+        trace.append((done, st["obj"]))
+        log(f"{done} iterations: f(w) = {st['obj']:.6e}, {elapsed * 1e3:.1f} ms")
+    wn = w.cpu().numpy()
+    plan.close()
+    print(json.dumps({
+        "metric": "SBB-NNLS solve: wall time per iteration (2 DSC + 1 or 2 WC + glue, all on the device)",
+        "value": round(elapsed * 1e3 / args.iterations, 4), "unit": "ms/iteration", "higher_is_better": False,
+        "n_gpus": 1, "iterations": args.iterations, "total_s": round(elapsed, 4), "dtype": "f32",
+        "data": "synthetic", "config": {"workload": f"{args.config} synthetic connectome", "nnz": c.nnz,
+                                        "voxel_order": args.voxel_order},
+        "objective": {"at_w0": trace[0][1], "last": trace[-1][1], "trace": trace},
+        "zero_weights_fraction": round(float(np.mean(wn == 0.0)), 4),
+    }), flush=True)
+
+
 def bench_adam(args):
     """Joint (w, D) Adam on ||y_obs - M(D) w||^2 through the library's
     differentiable DSC (forward DSC; backward WC + dictionary gradient), timed
@@ -400,9 +449,10 @@ def main():
                     help="also time the kernels with a 512 MB copy between steps (cold Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (calibrates the HBM byte counters)")
-    ap.add_argument("--workload", default="sbb", choices=["sbb", "adam", "batched"],
+    ap.add_argument("--workload", default="sbb", choices=["sbb", "adam", "batched", "solve"],
                     help="sbb: the headline SBB-NNLS iteration; adam: dictionary learning steps on the mid "
-                         "connectome; batched: uneven instances sharing D")
+                         "connectome; batched: uneven instances sharing D; solve: a whole SBB-NNLS solve")
+    ap.add_argument("--iterations", type=int, default=500, help="iterations of --workload solve")
     ap.add_argument("--adam-steps", type=int, default=200)
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--batch-scale", type=float, default=1.0, help="size factor of the batched instances")
@@ -421,6 +471,9 @@ def main():
         return
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "solve":
+        bench_solve(args)
         return
     if args.copy_probe:
         import torch
