@@ -162,11 +162,12 @@ life_status life_plan_batch(const life_dims *dims, int32_t n_inst, const int32_t
  * voxel processing positions (proc_pos, host, n_voxels: instance by instance,
  * each instance's block padded to whole 64-voxel chunks; Morton order inside an
  * instance when voxel_xyz is given, else voxel order), and the permutations and
- * offsets of life_plan_host over the union, with fascicles ranked by the mean
- * processing position of their voxels and those without nonzeros ranked at the
- * end of their own instance (so each instance's ranks are one contiguous
- * block).  Arguments and errors as life_plan_batch / life_plan_host; any output
- * may be NULL. */
+ * offsets of life_plan_host over the union.  Fascicles are ranked instance by
+ * instance (the instance is the major key, so instance k's fascicles take exactly
+ * the ranks [fas_off[k], fas_off[k+1])); inside an instance by the Z-order of the
+ * first and last processing positions of their voxels (ties by fascicle index),
+ * those without nonzeros last.  Arguments and errors as life_plan_batch /
+ * life_plan_host; any output may be NULL. */
 life_status life_plan_host_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
                                  const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
                                  const int32_t *fascicle, const int16_t *voxel_xyz, int32_t *proc_pos,
@@ -182,7 +183,9 @@ life_status life_plan_instances(life_plan_t plan, int32_t *n_inst);
  * times reps DSC+WC pairs on (D, w, y) and the fastest is kept.  Results do
  * not depend on the schedule.  D, w, y: device inputs as life_dsc/life_wc.
  * policy (host, optional): the chosen schedule (0, 1, 2).  Synchronizes the
- * device; uses the plan's workspace. */
+ * device; uses the plan's workspace.  The schedule is rewritten in place (same
+ * device addresses and launch grids), so graphs captured on the plan before the
+ * call stay valid and run the chosen schedule. */
 life_status life_plan_tune(life_plan_t plan, const float *D, const float *w, const float *y, int32_t reps,
                            int32_t *policy);
 

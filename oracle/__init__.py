@@ -46,17 +46,26 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "life_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SRC_PAR = os.path.join(_HERE, "life_oracle_par.c")
+_LIB_PAR = os.path.join(_HERE, "liboracle_par.so")
 _lib = None
+_lib_par = None
+
+
+def _gcc(src: str, lib: str, force: bool, extra=()) -> str:
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                        "-ffp-contract=off", *extra, src, "-o", tmp], check=True)
+        os.replace(tmp, lib)
+    return lib
 
 
 def build(force: bool = False) -> str:
-    """Compile life_oracle.c with gcc (plain -O2, no fast-math, sequential)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                        "-ffp-contract=off", _SRC, "-o", tmp], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile life_oracle.c (plain -O2, no fast-math, sequential) and the
+    multi-threaded life_oracle_par.c (the same, with OpenMP) with gcc."""
+    _gcc(_SRC_PAR, _LIB_PAR, force, ("-fopenmp",))
+    return _gcc(_SRC, _LIB, force)
 
 
 def _load():
@@ -74,6 +83,31 @@ def _load():
 
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
+
+
+def _load_par():
+    global _lib_par
+    if _lib_par is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PAR)
+        P = ctypes.c_void_p
+        lib.oracle_par_new.restype = P
+        lib.oracle_par_new.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+        lib.oracle_par_free.restype = None
+        lib.oracle_par_free.argtypes = [P]
+        for name in ("oracle_par_dsc", "oracle_par_wc"):
+            fn = getattr(lib, name)
+            fn.restype = None
+            fn.argtypes = [P, P, P, P]
+        lib.oracle_par_threads.restype = ctypes.c_int
+        lib.oracle_par_threads.argtypes = []
+        _lib_par = lib
+    return _lib_par
+
+
+def par_threads() -> int:
+    """OpenMP threads the multi-threaded oracle runs with (OMP_NUM_THREADS, else all cores)."""
+    return int(_load_par().oracle_par_threads())
 
 
 @dataclass
@@ -150,6 +184,10 @@ class Operator:
                           _ptr(self._phi64), _ptr(w64), _ptr(y64), _ptr(dD))
         return dD
 
+    def parallel(self) -> "ParOperator":
+        """The multi-threaded form of this operator (same results, bit for bit)."""
+        return ParOperator(self)
+
     def with_dictionary(self, D: np.ndarray) -> "Operator":
         """The same nonzeros with another dictionary."""
         return Operator(self.atom, self.voxel, self.fascicle, self._phi64, D, self.n_voxels, self.n_fascicles)
@@ -169,6 +207,50 @@ class Operator:
         """f(w) = 1/2 ||M w - b||^2  (eq. 2)."""
         r = self.dsc(w) - np.asarray(b, dtype=np.float64)
         return 0.5 * float(r @ r)
+
+
+class ParOperator:
+    """The same products as ``Operator.dsc`` / ``Operator.wc`` on OpenMP threads
+    (life_oracle_par.c): the nonzeros are grouped once by voxel and by fascicle
+    with a stable counting sort, so each output entry gets the additions of the
+    sequential loop in the same order, and the results are equal bit for bit."""
+
+    def __init__(self, op: Operator):
+        self.op = op
+        lib = _load_par()
+        self._h = lib.oracle_par_new(op.nnz, op.n_theta, op.n_voxels, op.n_fascicles, _ptr(op.atom),
+                                     _ptr(op.voxel), _ptr(op.fascicle), _ptr(op._phi64))
+        if not self._h:
+            raise MemoryError("oracle_par_new failed")
+
+    def close(self):
+        if self._h:
+            _load_par().oracle_par_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dsc(self, w: np.ndarray) -> np.ndarray:
+        op = self.op
+        w64 = np.ascontiguousarray(w, dtype=np.float64)
+        if w64.shape != (op.n_fascicles,):
+            raise ValueError("w has the wrong length")
+        y = np.empty(op.n_theta * op.n_voxels, dtype=np.float64)
+        _load_par().oracle_par_dsc(self._h, _ptr(op._D64), _ptr(w64), _ptr(y))
+        return y
+
+    def wc(self, y: np.ndarray) -> np.ndarray:
+        op = self.op
+        y64 = np.ascontiguousarray(y, dtype=np.float64)
+        if y64.shape != (op.n_theta * op.n_voxels,):
+            raise ValueError("y has the wrong length")
+        g = np.empty(op.n_fascicles, dtype=np.float64)
+        _load_par().oracle_par_wc(self._h, _ptr(op._D64), _ptr(y64), _ptr(g))
+        return g
 
 
 @dataclass

@@ -116,19 +116,6 @@ __device__ double block_sum_array(const double *a, int n)
     return r;
 }
 
-// Broadcast lane K of every aligned 8-lane group to the whole group (ds_swizzle,
-// bit-mask mode inside each 32-lane half: and 0x18, or K).
-template <int K>
-__device__ __forceinline__ int bcast8(int x)
-{
-    return __builtin_amdgcn_ds_swizzle(x, 0x18 | (K << 5));
-}
-template <int K>
-__device__ __forceinline__ float bcast8f(float x)
-{
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x18 | (K << 5)));
-}
-
 // ----------------------------------------------------------------------------- chunked kernels
 
 // Stage atoms [a0, a0 + nrow) of D into LDS rows of ROW floats (zero padded).
@@ -168,20 +155,6 @@ __device__ __forceinline__ int bcast16(int x)
 }
 template <int K>
 __device__ __forceinline__ float bcast16f(float x) { return dppf<0x150 + K>(x); }
-// value of lane (l ^ M) inside the row, M in {1, 2, 4, 8}
-template <int M>
-__device__ __forceinline__ float xor16(float x, int l16)
-{
-    if constexpr (M == 1) return dppf<0xB1>(x);                 // quad_perm [1,0,3,2]
-    else if constexpr (M == 2) return dppf<0x4E>(x);            // quad_perm [2,3,0,1]
-    else if constexpr (M == 8) return dppf<0x128>(x);           // row_ror:8
-    else {
-        const float up = dppf<0x104>(x);                        // row_shl:4 -> lane l gets l + 4
-        const float dn = dppf<0x114>(x);                        // row_shr:4 -> lane l gets l - 4
-        return (l16 & 4) ? dn : up;
-    }
-}
-
 constexpr int kSE = life::kStepEntries;      // entries per step (= lane groups per wave)
 constexpr int kGL = 64 / kSE;                // lanes per group (16)
 constexpr int kBatch = 64;                   // entries per batch: kGL steps
@@ -1417,21 +1390,21 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         ppos.resize((size_t)d.n_voxels);
         pvox.resize((size_t)n_pos);
         life::voxel_order(&d, voxel_xyz, n_inst, vox_off, ppos.data(), pvox.data());
-        std::vector<int32_t> empty_end;
+        std::vector<int32_t> fas_inst;
         if (batched) {
-            // fascicles without nonzeros rank at the end of their own instance
-            empty_end.resize((size_t)d.n_fascicles);
+            // each instance's fascicles take one contiguous block of ranks
+            fas_inst.resize((size_t)d.n_fascicles);
             int32_t base = 0;
             for (int k = 0; k < n_inst; ++k) {
                 base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
                 ichunk[(size_t)k + 1] = base / kChunkVoxels;
-                for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_end[(size_t)f] = base;
+                for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) fas_inst[(size_t)f] = k;
             }
         } else {
             ichunk[1] = n_chunks;
         }
         st = life::plan_host(&d, atom, voxel, fascicle, (voxel_xyz || batched) ? ppos.data() : nullptr, n_pos,
-                             batched ? empty_end.data() : nullptr, perm.data(), vptr.data(), rank.data(),
+                             batched ? fas_inst.data() : nullptr, perm.data(), vptr.data(), rank.data(),
                              wperm.data(), fptr.data());
         if (st != LIFE_OK) return st;
         for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
@@ -1476,7 +1449,14 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
                 const int64_t end = c + 1 < n_chunks ? wwork[(size_t)(c + 1) * per_chunk] : n_pad;
                 work[(size_t)c] = end - wwork[(size_t)c * per_chunk];
             }
+            // one grid length for every schedule policy (the longest map, the others
+            // padded with -1), so that re-scheduling keeps the map's address and the
+            // grid of launches already captured in a graph
+            size_t grid = 0;
+            for (int pol : {life::kScheduleIndex, life::kScheduleXcdCount, life::kScheduleXcdWork})
+                grid = std::max(grid, life::chunk_schedule(work, (life::SchedulePolicy)pol).size());
             cmap = life::chunk_schedule(work, life::kScheduleDefault);
+            cmap.resize(grid, -1);
             chunk_work.swap(work);
         }
     } catch (const std::bad_alloc &) {
@@ -1818,16 +1798,15 @@ extern "C" life_status life_plan_tune(life_plan_t plan, const float *D, const fl
     plan->profile = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
-    // install the schedule of policy pol (re-allocates the workgroup map)
+    // install the schedule of policy pol: the workgroup map is overwritten in place
+    // (same address, same grid length: every map is padded with -1 to chunk_grid)
     auto install = [&](int pol) -> hipError_t {
-        const std::vector<int32_t> map = life::chunk_schedule(plan->chunk_work, (life::SchedulePolicy)pol);
+        std::vector<int32_t> map = life::chunk_schedule(plan->chunk_work, (life::SchedulePolicy)pol);
+        if (map.size() > (size_t)plan->chunk_grid) return hipErrorInvalidValue;   // cannot happen
+        map.resize((size_t)plan->chunk_grid, -1);
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return e;
-        if (plan->chunk_map) (void)hipFree(plan->chunk_map);
-        plan->chunk_map = nullptr;
-        if ((e = dalloc(&plan->chunk_map, (int64_t)map.size())) != hipSuccess) return e;
         e = hipMemcpy(plan->chunk_map, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice);
-        plan->chunk_grid = (int)map.size();
         plan->schedule = pol;
         return e;
     };

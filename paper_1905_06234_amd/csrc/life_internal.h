@@ -35,11 +35,11 @@ void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int n_inst, const
                  int32_t *proc_pos, int32_t *proc_vox);
 
 // Host restructuring (see life_plan_host in life.h); proc_pos may be NULL (id
-// order); n_pos = number of processing positions; empty_end (NULL: fascicles
-// without nonzeros rank last) gives, for such a fascicle, the processing position
-// that ends its instance's block, after whose fascicles it ranks (batched plans).
+// order); n_pos = number of processing positions; fas_inst (batched plans, else
+// NULL) gives each fascicle's instance, the major key of the fascicle ranks, so
+// that each instance's fascicles take one contiguous block of ranks.
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
-                      const int32_t *proc_pos, int32_t n_pos, const int32_t *empty_end, int32_t *dsc_perm,
+                      const int32_t *proc_pos, int32_t n_pos, const int32_t *fas_inst, int32_t *dsc_perm,
                       int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr);
 
 // Work decomposition of the chunked (LDS-tiled) kernels, computed on the host.

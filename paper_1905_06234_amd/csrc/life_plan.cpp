@@ -105,12 +105,12 @@ uint64_t interleave2(uint32_t a, uint32_t b)
 // the weights of the fascicles crossing it; fascicles with nearby (lo, hi) cross
 // mostly the same chunks, so this order puts them in the same cache lines of w
 // (on the full synthetic connectome it halves the distinct (chunk, 128-byte line)
-// pairs against ordering by the mean position).  Z-order respects dominance, so
-// fascicles confined to a block of positions rank before those of a later block.
-// Fascicles without nonzeros rank last, or, with empty_end, right after the
-// fascicles of the block of positions that ends at empty_end[f].
+// pairs against ordering by the mean position).  Fascicles without nonzeros rank
+// last.  With fas_inst (batched plans) the instance of each fascicle is the major
+// key, so every instance's fascicles take one contiguous block of ranks (its
+// empty fascicles at the end of the block).
 void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fascicle, const int32_t *proc_pos,
-                    const int32_t *empty_end, int32_t *rank)
+                    const int32_t *fas_inst, int32_t *rank)
 {
     const int32_t nf = d->n_fascicles;
     std::vector<int32_t> lo(static_cast<size_t>(nf), INT32_MAX), hi(static_cast<size_t>(nf), -1);
@@ -120,19 +120,14 @@ void fascicle_ranks(const life_dims *d, const int32_t *voxel, const int32_t *fas
         hi[fascicle[c]] = std::max(hi[fascicle[c]], p);
     }
     std::vector<uint64_t> key(static_cast<size_t>(nf));
-    for (int32_t f = 0; f < nf; ++f) {
-        if (hi[f] >= 0) {
-            key[f] = 2 * interleave2(static_cast<uint32_t>(lo[f]), static_cast<uint32_t>(hi[f]));
-        } else if (empty_end) {
-            const uint32_t e = static_cast<uint32_t>(empty_end[f] - 1);
-            key[f] = 2 * interleave2(e, e) + 1;
-        } else {
-            key[f] = UINT64_MAX;
-        }
-    }
+    for (int32_t f = 0; f < nf; ++f)
+        key[f] = hi[f] >= 0 ? interleave2(static_cast<uint32_t>(lo[f]), static_cast<uint32_t>(hi[f])) : UINT64_MAX;
     std::vector<int32_t> order(static_cast<size_t>(nf));
     for (int32_t f = 0; f < nf; ++f) order[f] = f;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int32_t ia = fas_inst ? fas_inst[a] : 0, ib = fas_inst ? fas_inst[b] : 0;
+        return ia != ib ? ia < ib : key[a] < key[b];
+    });
     for (int32_t r = 0; r < nf; ++r) rank[order[r]] = r;
 }
 
@@ -195,7 +190,7 @@ void voxel_order(const life_dims *d, const int16_t *voxel_xyz, int n_inst, const
 }
 
 life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
-                      const int32_t *proc_pos, int32_t n_pos, const int32_t *empty_end, int32_t *dsc_perm,
+                      const int32_t *proc_pos, int32_t n_pos, const int32_t *fas_inst, int32_t *dsc_perm,
                       int32_t *vox_ptr, int32_t *fas_rank, int32_t *wc_perm, int32_t *fas_ptr)
 {
     life_status st = validate_dims(d);
@@ -218,7 +213,7 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
             segment_offsets(keys.data(), n, d->n_voxels, vox_ptr);
         }
         std::vector<int32_t> rank(static_cast<size_t>(d->n_fascicles));
-        fascicle_ranks(d, voxel, fascicle, proc_pos, empty_end, rank.data());
+        fascicle_ranks(d, voxel, fascicle, proc_pos, fas_inst, rank.data());
         if (fas_rank && d->n_fascicles)
             std::memcpy(fas_rank, rank.data(), sizeof(int32_t) * static_cast<size_t>(d->n_fascicles));
         if (wc_perm || fas_ptr) {
@@ -478,15 +473,11 @@ extern "C" life_status life_plan_host_batch(const life_dims *dims, int32_t n_ins
         if (n_pos < 0) return LIFE_ERANGE;
         std::vector<int32_t> pos((size_t)dims->n_voxels);
         life::voxel_order(dims, voxel_xyz, n_inst, vox_off, pos.data(), nullptr);
-        std::vector<int32_t> empty_end((size_t)dims->n_fascicles);
-        int64_t base = 0;
-        for (int k = 0; k < n_inst; ++k) {
-            const int32_t nvk = vox_off[k + 1] - vox_off[k];
-            base += n_inst > 1 ? (nvk + life::kChunkVoxels - 1) / life::kChunkVoxels * life::kChunkVoxels : nvk;
-            for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) empty_end[(size_t)f] = (int32_t)base;
-        }
+        std::vector<int32_t> fas_inst((size_t)dims->n_fascicles);
+        for (int k = 0; k < n_inst; ++k)
+            for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) fas_inst[(size_t)f] = k;
         if (proc_pos && dims->n_voxels) std::memcpy(proc_pos, pos.data(), sizeof(int32_t) * pos.size());
-        return life::plan_host(dims, atom, voxel, fascicle, pos.data(), n_pos, empty_end.data(), dsc_perm, vox_ptr,
+        return life::plan_host(dims, atom, voxel, fascicle, pos.data(), n_pos, fas_inst.data(), dsc_perm, vox_ptr,
                                fas_rank, wc_perm, fas_ptr);
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;

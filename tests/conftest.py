@@ -55,11 +55,10 @@ def morton_positions(xyz):
     return pos
 
 
-def fascicle_keys(fascicle, vpp, n_fascicles, empty_end=None):
-    """Rank keys of the fascicles: 2 * Z(lo, hi), where lo, hi are the first and last
+def fascicle_keys(fascicle, vpp, n_fascicles):
+    """Rank keys of the fascicles: Z(lo, hi), where lo, hi are the first and last
     processing positions of a fascicle's voxels and Z puts bit i of lo at bit 2i and
-    bit i of hi at bit 2i+1; a fascicle without nonzeros gets 2 * Z(e, e) + 1 with
-    e = empty_end - 1 when its block end is given, else the largest key."""
+    bit i of hi at bit 2i+1; a fascicle without nonzeros gets the largest key."""
     lo = np.full(n_fascicles, np.iinfo(np.int64).max, np.int64)
     hi = np.full(n_fascicles, -1, np.int64)
     np.minimum.at(lo, fascicle, vpp)
@@ -67,19 +66,12 @@ def fascicle_keys(fascicle, vpp, n_fascicles, empty_end=None):
     has = hi >= 0
     a = np.where(has, lo, 0).astype(np.uint64)
     b = np.where(has, hi, 0).astype(np.uint64)
-    if empty_end is not None:
-        e = np.asarray(empty_end, np.int64) - 1
-        a = np.where(has, a, e.astype(np.uint64))
-        b = np.where(has, b, e.astype(np.uint64))
     z = np.zeros(n_fascicles, np.uint64)
     for i in range(32):
         one = np.uint64(1)
         z |= ((a >> np.uint64(i)) & one) << np.uint64(2 * i)
         z |= ((b >> np.uint64(i)) & one) << np.uint64(2 * i + 1)
-    key = z * np.uint64(2)
-    if empty_end is None:
-        return np.where(has, key, np.iinfo(np.uint64).max)
-    return np.where(has, key, key + np.uint64(1))
+    return np.where(has, z, np.iinfo(np.uint64).max)
 
 
 def reference_plan(c, xyz=None):

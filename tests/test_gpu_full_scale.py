@@ -1,11 +1,16 @@
 """GPU parity at the full synthetic scale (N_theta = 96, N_a = 1057, ~300k voxels,
 1.5M fascicles, ~90M nonzeros), with the plan the benchmark times (Morton voxel
-order).  The FP64 oracle cannot run whole operators at this size in test time,
-so outputs are checked on samples it computes one by one: a DSC row y_v needs
-only the nonzeros of voxel v, a WC entry g_f only those of fascicle f.  The
-SBB-NNLS step is checked by a property that holds at any size: every fascicle
-moves along its own projected gradient with one common step length, clipped at
-zero (eqs. 5-8), with the gradient recomputed by the oracle for a sample.
+order).
+
+Whole outputs are compared with the multi-threaded FP64 oracle (equal, bit for
+bit, to the sequential one): DSC and WC vectors, the FP32 adjoint identity, and
+SBB-NNLS iterations 0 and 1 teacher-forced from the oracle's iterate (w, alpha,
+f and ||g~||^2), all at normwise relative error <= 1e-5.  Samples the oracle
+computes one by one (a DSC row y_v needs only the nonzeros of voxel v, a WC
+entry g_f only those of fascicle f) check single entries, including the
+heaviest voxel and the longest fascicle, and a property that holds at any size
+checks one step: every fascicle moves along its own projected gradient with one
+common step length, clipped at zero (eqs. 5-8).
 """
 import numpy as np
 import pytest
@@ -111,3 +116,86 @@ def test_full_sbb_step_moves_along_projected_gradient(full):
         assert abs(alpha - s["alpha"]) <= 1e-3 * s["alpha"], (alpha, s["alpha"])
         still = gt == 0
         assert np.array_equal(w1[fs][still], w0[fs][still].astype(np.float64))
+
+
+# ----------------------------------------------------------------------------- whole outputs
+
+@pytest.fixture(scope="module")
+def full_ref(full):
+    c, plan, dev = full
+    print("[full] grouping the nonzeros for the multi-threaded oracle", flush=True)
+    op = oracle.Operator.from_connectome(c)
+    par = op.parallel()
+    print(f"[full] oracle ready ({oracle.par_threads()} threads)", flush=True)
+    yield op, par
+    par.close()
+
+
+def _np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def test_full_dsc_whole(full, full_ref):
+    c, plan, dev = full
+    _, par = full_ref
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    rng = np.random.default_rng(21)
+    signed = rng.standard_normal(c.n_fascicles).astype(np.float32)
+    for label, w in (("w0", c.w0), ("signed", signed)):
+        y = plan.dsc(D, torch.from_numpy(np.ascontiguousarray(w)).to(dev))
+        err = relerr(_np(y), par.dsc(w))
+        print(f"[full] DSC {label}: normwise relative error {err:.3e}", flush=True)
+        assert err <= TOL, label
+
+
+def test_full_wc_whole(full, full_ref):
+    c, plan, dev = full
+    _, par = full_ref
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    g = plan.wc(D, torch.from_numpy(c.noise).to(dev))
+    err = relerr(_np(g), par.wc(c.noise))
+    print(f"[full] WC: normwise relative error {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+def test_full_adjoint_identity_fp32(full):
+    """<M w, y> = <w, M^T y> for the device products on the whole operator, relative
+    to |<M w, y>| (random-sign y: the sums cancel, so a rounding bias in either product
+    shows), and <w, M^T (M w)> = ||M w||^2."""
+    c, plan, dev = full
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    w = torch.from_numpy(c.w0).to(dev)
+    y = torch.from_numpy(c.noise).to(dev)
+    mw = plan.dsc(D, w)
+    lhs = float(_np(mw) @ _np(y))
+    rhs = float(_np(w) @ _np(plan.wc(D, y)))
+    print(f"[full] adjoint residual {abs(lhs - rhs) / abs(lhs):.3e}", flush=True)
+    assert abs(lhs - rhs) <= TOL * abs(lhs)
+    n2, rhs2 = float(_np(mw) @ _np(mw)), float(_np(w) @ _np(plan.wc(D, mw)))
+    print(f"[full] ||Mw||^2 residual {abs(n2 - rhs2) / n2:.3e}", flush=True)
+    assert abs(n2 - rhs2) <= TOL * n2
+
+
+def test_full_sbb_steps_teacher_forced(full, full_ref):
+    """Iterations 0 (even: second WC, alpha = <v',v'>/<v'',v''>) and 1 (odd: alpha =
+    <g~,g~>/<v',v'>) of Algorithm 1 on the whole problem, each from the oracle's own
+    iterate, against oracle.sbb_step on b = M w_true + 5% noise."""
+    c, plan, dev = full
+    _, par = full_ref
+    b32 = oracle.noisy_signal(par, c.w_true, c.noise).astype(np.float32)
+    D = torch.from_numpy(c.D.ravel()).to(dev)
+    b = torch.from_numpy(b32).to(dev)
+    w = c.w0.astype(np.float32)
+    for i in (0, 1):
+        ref = oracle.sbb_step(par, w, i, b32)
+        wt = torch.from_numpy(w.copy()).to(dev)
+        st = life.new_state(dev, iteration=i)
+        plan.sbbnnls_step(D, b, wt, st)
+        s = life.read_state(st)
+        errs = {"w": relerr(_np(wt), ref.w), "alpha": abs(s["alpha"] - ref.alpha) / ref.alpha,
+                "f": abs(s["obj"] - ref.f) / ref.f, "gt2": abs(s["gt_norm2"] - ref.gt_norm2) / ref.gt_norm2,
+                "num": abs(s["num"] - ref.num) / ref.num, "den": abs(s["den"] - ref.den) / ref.den}
+        print(f"[full] SBB step {i}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+        assert s["iter"] == i + 1
+        assert all(v <= TOL for v in errs.values()), (i, errs)
+        w = ref.w.astype(np.float32)

@@ -474,3 +474,34 @@ def test_dd_pin_catches_planted_mistakes():
     assert abs(float(np.sum(op.dd(w, ybar) * E)) - rhs) <= 1e-10 * abs(rhs)
     for name, dD in mutants.items():
         assert abs(float(np.sum(dD * E)) - rhs) > 1e-6 * abs(rhs), name
+
+
+# ----------------------------------------------------------------------------- multi-threaded oracle
+
+@pytest.mark.parametrize("case", ["tiny", "dup", "ragged", "empty", "sparsevox"])
+def test_parallel_oracle_equals_sequential(case):
+    """The OpenMP oracle (grouped copies, one thread per output entry) gives the
+    sequential oracle's DSC and WC bit for bit: each entry receives the same
+    additions in the same (input) order."""
+    if case == "tiny":
+        c = connectome("tiny")
+    else:
+        shape = {"dup": (96, 57, 300, 400, 40_000, True), "ragged": (33, 9, 70, 100, 3000, False),
+                 "empty": (16, 64, 50, 20, 0, False), "sparsevox": (8, 5, 5000, 30, 200, False)}[case]
+        nt, na, nv, nf, nnz, dup = shape
+        c = synth.random_coo(nt, na, nv, nf, nnz, seed=17, duplicates=dup)
+    op = oracle.Operator.from_connectome(c)
+    par = op.parallel()
+    rng = np.random.default_rng(3)
+    for w in (c.w0, rng.standard_normal(c.n_fascicles)):
+        a, b = op.dsc(w), par.dsc(w)
+        assert np.array_equal(a, b) and relerr(b, a) <= 1e-12
+    for y in (c.noise, rng.standard_normal(c.n_theta * c.n_voxels)):
+        a, b = op.wc(y), par.wc(y)
+        assert np.array_equal(a, b) and relerr(b, a) <= 1e-12
+    # the SBB step runs on either form
+    b32 = oracle.noisy_signal(op, c.w_true, c.noise)
+    s1, s2 = oracle.sbb_step(op, c.w0, 0, b32), oracle.sbb_step(par, c.w0, 0, b32)
+    assert np.array_equal(s1.w, s2.w) and s1.alpha == s2.alpha
+    assert oracle.par_threads() >= 1
+    par.close()

@@ -79,7 +79,7 @@ def test_fascicle_rank_key_pinned():
     p = life.plan_host(2, 1, 8, 4, np.zeros(5, np.int16), voxel, fascicle)
     assert np.array_equal(p["fas_rank"], [1, 2, 0, 3])
     from conftest import fascicle_keys
-    assert np.array_equal(fascicle_keys(fascicle, voxel, 4)[:3], [74, 80, 6])
+    assert np.array_equal(fascicle_keys(fascicle, voxel, 4)[:3], [37, 40, 3])
 
 
 def test_negative_coordinate_rejected():
@@ -153,23 +153,24 @@ def _batch_instances():
     return b[:2] + [r] + b[2:]
 
 
-def _reference_batch_plan(inst):
+def _reference_batch_plan(inst, raw=None):
     """Batched restructuring computed independently: positions instance by instance
-    (Morton inside, blocks padded to 64), ranks by fascicle_keys (empty fascicles at
-    the end of their instance), then the same lexsorts as reference_plan."""
+    (Morton inside, blocks padded to 64), ranks by (instance, fascicle_keys, index)
+    (so empty fascicles end their instance's block), then the same lexsorts as
+    reference_plan."""
     from conftest import fascicle_keys, morton_positions
-    dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = life.concat_instances(inst)
+    dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = raw or life.concat_instances(inst)
     pp = np.empty(dims.n_voxels, np.int64)
-    empty_end = np.empty(dims.n_fascicles, np.int64)
+    inst_of = np.empty(dims.n_fascicles, np.int64)
     base = 0
-    for k in range(len(inst)):
+    for k in range(len(vox_off) - 1):
         v0, v1 = vox_off[k], vox_off[k + 1]
         pp[v0:v1] = base + morton_positions(xyz[v0:v1])
         base += -(-(v1 - v0) // 64) * 64
-        empty_end[fas_off[k]:fas_off[k + 1]] = base
+        inst_of[fas_off[k]:fas_off[k + 1]] = k
     pos = np.arange(dims.nnz)
-    key = fascicle_keys(fascicle, pp[voxel], dims.n_fascicles, empty_end)
-    order = np.argsort(key, kind="stable")
+    key = fascicle_keys(fascicle, pp[voxel], dims.n_fascicles)
+    order = np.lexsort((np.arange(dims.n_fascicles), key, inst_of))
     rank = np.empty(dims.n_fascicles, np.int64)
     rank[order] = np.arange(dims.n_fascicles)
     dsc = np.lexsort((pos, fascicle, atom, voxel))
@@ -220,3 +221,25 @@ def test_batch_plan_needs_chunked_geometry():
     with pytest.raises(life.LifeError) as e:
         life.Plan.batch([a, b])
     assert e.value.status == 1
+
+
+def test_batch_ranks_with_empty_instances():
+    """Instances without voxels (leading and in the middle) and instances whose
+    fascicles are all empty: every instance's ranks are exactly its own block
+    [fas_off[k], fas_off[k+1]), which the batched step kernels rely on."""
+    inst = _batch_instances()[:2]
+    dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = life.concat_instances(inst)
+    # insert an instance with no voxels and 3 fascicles before each real instance
+    vo = np.array([0, 0, vox_off[1], vox_off[1], vox_off[2]], np.int32)
+    shift = np.array([3, 6])
+    fo = np.array([0, 3, 3 + fas_off[1], 6 + fas_off[1], 6 + fas_off[2]], np.int32)
+    k_of = np.searchsorted(fas_off, fascicle, side="right") - 1
+    fas2 = (fascicle + shift[k_of]).astype(np.int32)
+    d2 = life.Dims(dims.n_theta, dims.n_atoms, dims.n_voxels, int(fo[-1]), dims.nnz)
+    raw = (d2, vo, fo, atom, voxel, fas2, phi, xyz)
+    p = life.plan_host_batch(None, raw=raw)
+    for k in range(len(vo) - 1):
+        assert np.array_equal(np.sort(p["fas_rank"][fo[k]:fo[k + 1]]), np.arange(fo[k], fo[k + 1])), k
+    ref = _reference_batch_plan(None, raw=raw)
+    for key in ("proc_pos", "dsc_perm", "vox_ptr", "fas_rank", "wc_perm", "fas_ptr"):
+        assert np.array_equal(p[key], ref[key]), key
