@@ -27,8 +27,14 @@
  *     allocate, free or synchronize.
  *   - Results are deterministic: the same plan and inputs give bitwise equal
  *     outputs on every call (fixed reduction orders, no atomics).
- *   - A plan owns a workspace; calls that share one plan must not overlap in
- *     time (enqueue them on one stream, or order the streams).
+ *   - Workspace: everything a call writes besides its outputs (weights in the
+ *     plan's fascicle order, WC pass-1 values, the SBB vectors and partial sums).
+ *     A plan owns one, used by the calls that take no scratch argument; calls
+ *     that share it must not overlap in time (enqueue them on one stream, or
+ *     order the streams).  life_dsc_ws, life_wc_ws and life_sbbnnls_step_ws take
+ *     the caller's scratch instead (life_plan_scratch_bytes bytes), so one plan
+ *     serves several streams at once, one scratch buffer per stream.  The plan's
+ *     own arrays are only read by these calls.
  *   - Every function returns a life_status; on an error nothing is enqueued
  *     and outputs are left untouched unless stated.
  */
@@ -226,6 +232,23 @@ life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y,
  * Errors: as life_dsc. */
 life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream);
 
+/* Bytes of the caller scratch that life_dsc_ws, life_wc_ws and
+ * life_sbbnnls_step_ws take (the size of the plan's own workspace).  *bytes
+ * (host) is written.  Errors: LIFE_EINVAL (NULL argument). */
+life_status life_plan_scratch_bytes(life_plan_t plan, uint64_t *bytes);
+
+/* life_dsc and life_wc with the caller's scratch in place of the plan's
+ * workspace.  scratch (device, 256-byte aligned, scratch_bytes >=
+ * life_plan_scratch_bytes) is overwritten; it must not be used by another call
+ * in flight.  scratch = NULL selects the plan's workspace (same as life_dsc /
+ * life_wc).  Results are bitwise the same as those of life_dsc / life_wc.
+ * Errors: as life_dsc; LIFE_EINVAL also for a scratch that is too small or
+ * misaligned. */
+life_status life_dsc_ws(life_plan_t plan, const float *D, const float *w, float *y, void *scratch,
+                        uint64_t scratch_bytes, void *stream);
+life_status life_wc_ws(life_plan_t plan, const float *D, const float *y, float *g, void *scratch,
+                       uint64_t scratch_bytes, void *stream);
+
 /* One SBB-NNLS iteration, Algorithm 1 (Sec. 2.1) with eqs. 5-6:
  *   r  = M w - b;   g = M^T r  (the gradient, eq. 6);
  *   g~ = g with g_f set to 0 where w_f = 0 and g_f > 0 (projected gradient);
@@ -242,6 +265,13 @@ life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, 
  * Errors: as life_dsc. */
 life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
                               life_sbb_state *state, void *stream);
+
+/* life_sbbnnls_step with the caller's scratch in place of the plan's workspace
+ * (arguments as life_dsc_ws: scratch is device memory of at least
+ * life_plan_scratch_bytes bytes, 256-byte aligned; NULL = the plan's own).
+ * Bitwise the same results as life_sbbnnls_step.  Errors: as life_dsc_ws. */
+life_status life_sbbnnls_step_ws(life_plan_t plan, const float *D, const float *b, float *w,
+                                 life_sbb_state *state, void *scratch, uint64_t scratch_bytes, void *stream);
 
 /* One SBB-NNLS iteration with the step lengths of eqs. 7-8 as printed, i.e. the
  * classic lagged Barzilai-Borwein form: alpha^(i) is evaluated at q, the

@@ -33,6 +33,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -1032,6 +1033,24 @@ int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ============================================================================= plan object
 
+// Everything the enqueue calls write besides their outputs.  One contiguous block
+// (life_plan_scratch_bytes) carved into regions of 256-byte aligned arrays; the
+// plan owns one, and the *_ws calls take the caller's, so that one plan can serve
+// several streams at once.
+struct Workspace {
+    float *w_rank = nullptr;      // [Nf] weights (or g~) in fascicle-rank order
+    h8 *dt_frag = nullptr;        // [n_tiles][dt_ab][dt_ks][2][64] split D^T operands of WC pass 1
+    float *dt_scale = nullptr;    // [n_tiles][dt_ab][32]
+    float *z = nullptr;           // [max(nnz, n_pad)] WC pass-1 values
+    float *r = nullptr, *vp = nullptr;                                // [Nt*Nv] SBB residual, M q
+    float *g = nullptr, *gt = nullptr, *vpp = nullptr, *q = nullptr;  // [Nf] SBB vectors
+    double *part = nullptr;       // 5 regions of part_stride partial sums
+    float *dd_part = nullptr;     // dictionary-gradient partials
+};
+
+// Regions of the workspace a call needs.
+enum : unsigned { kWsDsc = 1u, kWsWc = 2u, kWsSbb = 4u, kWsDd = 8u, kWsAll = 15u };
+
 struct life_plan_s {
     life_dims dims{};
     int device = 0;
@@ -1061,24 +1080,19 @@ struct life_plan_s {
     int dt_ab = 0, dt_ks = 0;     // atom blocks of 32 per tile, k-steps of 16 theta
     int wcz_cap = 0;              // floats of LDS that stage a tile's z values (0: none)
     size_t wcz_lds = 0;
-    h8 *dt_frag = nullptr;        // [n_tiles][dt_ab][dt_ks][2][64]
-    float *dt_scale = nullptr;    // [n_tiles][dt_ab][32]
     // fascicles are processed in rank order (fas_v holds ranks)
     int32_t *fas_rank = nullptr;  // [Nf] rank of each fascicle
     int32_t *fas_ext = nullptr;   // [Nf] fascicle of each rank
     // WC order (rank, voxel, atom, input position) as DSC positions
     int32_t *fas_ptr = nullptr;   // [Nf + 1]
     int32_t *wc_perm = nullptr;   // [nnz]
-    // workspace
-    float *w_rank = nullptr;      // [Nf] weights in rank order
-    float *z = nullptr;           // [nnz]
-    float *r = nullptr, *vp = nullptr;                  // [Nt*Nv]
-    float *g = nullptr, *gt = nullptr, *vpp = nullptr, *q = nullptr;  // [Nf]
-    double *part = nullptr;       // 5 regions of part_stride
-    int64_t part_stride = 0;
+    // the plan's own workspace (calls given no caller scratch use it)
+    Workspace ws;
+    void *ws_base = nullptr;
+    int64_t part_stride = 0;      // doubles per partial-sum region of the workspace
     // dictionary gradient: chunked (per tile and chunk group partials) ...
     int dd_groups = 0, dd_tap = 0, dd_nbw = 0, dd_span = 1;   // dd tile = dd_span plan tiles
-    float *dd_part = nullptr;     // [T][groups][dd_tap][16 ceil(Nt/16)]
+    int64_t dd_floats = 0;        // [T][groups][dd_tap][16 ceil(Nt/16)] partials in the workspace
     // ... or generic (atom-major copy of the nonzeros)
     int32_t *a_ptr = nullptr;     // [Na + 1]
     int32_t *a_vox = nullptr, *a_fas = nullptr;   // [nnz] voxel, fascicle rank
@@ -1119,10 +1133,9 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_plan(life_plan_s *p)
 {
-    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c, p->fas_c,
-                    p->phi_c, p->z_pos, p->wc_perm_z, p->tile_z, p->dt_frag, p->dt_scale, p->fas_rank, p->fas_ext,
-                    p->fas_ptr, p->wc_perm, p->w_rank, p->z, p->r, p->vp, p->g, p->gt, p->vpp, p->q, p->part,
-                    p->dd_part, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
+    void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c,
+                    p->fas_c, p->phi_c, p->z_pos, p->wc_perm_z, p->tile_z, p->fas_rank, p->fas_ext, p->fas_ptr,
+                    p->wc_perm, p->ws_base, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->events) {
@@ -1130,6 +1143,42 @@ void free_plan(life_plan_s *p)
         (void)hipEventDestroy(e.second.second);
     }
     delete p;
+}
+
+// Carve the regions a call needs (mask of kWs*) out of base (NULL: sizes only);
+// returns the bytes they take.  Every region starts on a 256-byte boundary.
+size_t workspace_layout(const life_plan_s *p, unsigned need, char *base, Workspace *ws)
+{
+    const life_dims &d = p->dims;
+    const int64_t nf = d.n_fascicles, nsig = (int64_t)d.n_theta * d.n_voxels;
+    size_t off = 0;
+    auto take = [&](auto **ptr, int64_t n, size_t elem) {
+        off = (off + 255) / 256 * 256;
+        using T = std::remove_reference_t<decltype(**ptr)>;
+        *ptr = (base && n > 0) ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += (size_t)std::max<int64_t>(n, 0) * elem;
+    };
+    Workspace w;
+    if (need & (kWsDsc | kWsSbb | kWsDd)) take(&w.w_rank, nf, sizeof(float));
+    if (need & (kWsWc | kWsSbb)) {
+        if (p->n_chunks > 0) {
+            take(&w.dt_frag, (int64_t)p->tile.n_tiles * p->dt_ab * p->dt_ks * 2 * 64, sizeof(h8));
+            take(&w.dt_scale, (int64_t)p->tile.n_tiles * p->dt_ab * 32, sizeof(float));
+        }
+        take(&w.z, std::max<int64_t>(d.nnz, p->n_pad), sizeof(float));
+    }
+    if (need & kWsSbb) {
+        take(&w.r, nsig, sizeof(float));
+        take(&w.vp, nsig, sizeof(float));
+        take(&w.g, nf, sizeof(float));
+        take(&w.gt, nf, sizeof(float));
+        take(&w.vpp, nf, sizeof(float));
+        take(&w.q, nf, sizeof(float));
+        take(&w.part, 5 * p->part_stride, sizeof(double));
+    }
+    if (need & kWsDd) take(&w.dd_part, p->dd_floats, sizeof(float));
+    if (ws) *ws = w;
+    return (off + 255) / 256 * 256;
 }
 
 int slots_for(int nth)
@@ -1255,8 +1304,8 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
     });
 }
 
-life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g, const int32_t *gmap,
-                       double *part, Gate gate, hipStream_t s, bool split_d = true)
+life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, const float *y, float *g,
+                       const int32_t *gmap, double *part, Gate gate, hipStream_t s, bool split_d = true)
 {
     const int nv = p->dims.n_voxels, nf = p->dims.n_fascicles, nth = p->dims.n_theta;
     life_status st = LIFE_OK;
@@ -1267,19 +1316,19 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
             const int T = p->tile.n_tiles, AB = p->dt_ab, KS = p->dt_ks, TA = p->tile.tile_atoms;
             st = launch(p, kind, s, [&] {
                 if (split_d)
-                    k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, p->dt_frag, p->dt_scale,
+                    k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, ws.dt_frag, ws.dt_scale,
                                                                                          nth, p->dims.n_atoms, T, TA,
                                                                                          AB, KS, gate);
                 k_wcz_mfma<<<p->chunk_grid, kWG, p->wcz_lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work, p->atom_c,
-                                                                  p->phi_c, p->z_pos, p->tile_z, p->dt_frag,
-                                                                  p->dt_scale, y, p->z, nth, T, TA, AB, KS,
+                                                                  p->phi_c, p->z_pos, p->tile_z, ws.dt_frag,
+                                                                  ws.dt_scale, y, ws.z, nth, T, TA, AB, KS,
                                                                   p->wcz_cap, gate);
             });
         } else {
             const int grid = cdiv(nv, kSegPerBlock);
             st = launch(p, kind, s, [&] {
                 LIFE_DISPATCH_SLOTS(p->slots, k_wc_z, grid, kBlock, 0, s>>>(p->vox_ptr, p->atom_v, p->phi_v, D, y,
-                                                                            p->z, nth, nv, gate))
+                                                                            ws.z, nth, nv, gate))
             });
         }
         if (st != LIFE_OK) return st;
@@ -1287,24 +1336,24 @@ life_status enqueue_wc(life_plan_s *p, const float *D, const float *y, float *g,
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
         st = launch(p, gate.st ? LIFE_K_WC_SUM_2ND : LIFE_K_WC_SUM, s, [&] {
-            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_z : p->wc_perm, p->z, gmap, g,
+            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_z : p->wc_perm, ws.z, gmap, g,
                                              part, nf, gate);
         });
     }
     return st;
 }
 
-life_status enqueue_gather(life_plan_s *p, const float *w, hipStream_t s)
+life_status enqueue_gather(life_plan_s *p, const Workspace &ws, const float *w, hipStream_t s)
 {
     const int nf = p->dims.n_fascicles;
     if (nf == 0) return LIFE_OK;
     return launch(p, LIFE_K_PERMUTE, s, [&] {
-        k_gather<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, p->fas_ext, p->w_rank, nf);
+        k_gather<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, p->fas_ext, ws.w_rank, nf);
     });
 }
 
 // dD from w_rank (weights already in rank order) and ybar.
-life_status enqueue_dd(life_plan_s *p, const float *ybar, float *dD, hipStream_t s)
+life_status enqueue_dd(life_plan_s *p, const Workspace &ws, const float *ybar, float *dD, hipStream_t s)
 {
     const life_dims &d = p->dims;
     const int nth = d.n_theta, na = d.n_atoms;
@@ -1314,19 +1363,19 @@ life_status enqueue_dd(life_plan_s *p, const float *ybar, float *dD, hipStream_t
         const size_t lds = (size_t)(TAP + (nth + 15) / 16 * 16) * kPsiStride * sizeof(float);
         life_status st = launch(p, LIFE_K_DD, s, [&] {
             LIFE_DISPATCH_NBW(p->dd_nbw, k_dd_chunk, DT * G, kWG, lds, s>>>(p->chunk_vox, p->wave_work, p->atom_c,
-                                                                          p->fas_c, p->phi_c, p->w_rank, ybar,
-                                                                          p->dd_part, nth, T, TA, TAP, S,
+                                                                          p->fas_c, p->phi_c, ws.w_rank, ybar,
+                                                                          ws.dd_part, nth, T, TA, TAP, S,
                                                                           p->n_chunks, G))
         });
         if (st != LIFE_OK) return st;
         // a dd tile holds S TA atoms
         return launch(p, LIFE_K_DD_REDUCE, s, [&] {
-            k_dd_reduce<<<cdiv((int64_t)na * nth, kBlock), kBlock, 0, s>>>(p->dd_part, dD, nth, na, S * TA, TAP, G);
+            k_dd_reduce<<<cdiv((int64_t)na * nth, kBlock), kBlock, 0, s>>>(ws.dd_part, dD, nth, na, S * TA, TAP, G);
         });
     }
     return launch(p, LIFE_K_DD, s, [&] {
         LIFE_DISPATCH_SLOTS(p->slots, k_dd_atom, na, kBlock, 0, s>>>(p->a_ptr, p->a_vox, p->a_fas, p->a_phi,
-                                                                     p->w_rank, ybar, dD, nth, na))
+                                                                     ws.w_rank, ybar, dD, nth, na))
     });
 }
 
@@ -1476,11 +1525,9 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     p->n_pad = n_pad;
     p->chunk_grid = (int)cmap.size();
     p->chunk_work.swap(chunk_work);
-    const int64_t nsig = (int64_t)d.n_theta * d.n_voxels;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
     p->part_stride = nb;
-    int64_t dd_floats = 0;
     if (n_chunks > 0) {
         const int T = tg.n_tiles;
         // the widest span of tiles whose block fits the LDS and the accumulator variants
@@ -1499,7 +1546,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         p->dd_groups = std::max(1, std::min(n_chunks, 512 / DT));
         const int nb_blocks = nt16 / 16 * (p->dd_tap / 16);
         p->dd_nbw = dd_nbw_variant((nb_blocks + kChunkWaves - 1) / kChunkWaves);
-        dd_floats = (int64_t)DT * p->dd_groups * p->dd_tap * nt16;
+        p->dd_floats = (int64_t)DT * p->dd_groups * p->dd_tap * nt16;
         p->dt_ab = (tg.tile_atoms + 31) / 32;
         p->dt_ks = (d.n_theta + 15) / 16;
         p->wcz_lds = (size_t)p->dt_ab * 32 * kPS * sizeof(float) +
@@ -1529,24 +1576,16 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     chk(dalloc(&p->z_pos, (int64_t)zpos.size()));
     chk(dalloc(&p->wc_perm_z, (int64_t)wperm_z.size()));
     chk(dalloc(&p->tile_z, (int64_t)tilez.size()));
-    if (n_chunks > 0) {
-        chk(dalloc(&p->dt_frag, (int64_t)tg.n_tiles * p->dt_ab * p->dt_ks * 2 * 64));
-        chk(dalloc(&p->dt_scale, (int64_t)tg.n_tiles * p->dt_ab * 32));
-    }
     chk(dalloc(&p->fas_rank, d.n_fascicles));
     chk(dalloc(&p->fas_ext, d.n_fascicles));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
     chk(dalloc(&p->wc_perm, d.nnz));
-    chk(dalloc(&p->w_rank, d.n_fascicles));
-    chk(dalloc(&p->z, std::max<int64_t>(d.nnz, n_pad)));
-    chk(dalloc(&p->r, nsig));
-    chk(dalloc(&p->vp, nsig));
-    chk(dalloc(&p->g, d.n_fascicles));
-    chk(dalloc(&p->gt, d.n_fascicles));
-    chk(dalloc(&p->vpp, d.n_fascicles));
-    chk(dalloc(&p->q, d.n_fascicles));
-    chk(dalloc(&p->part, 5 * nb));
-    chk(dalloc(&p->dd_part, dd_floats));
+    {
+        char *base = nullptr;
+        chk(dalloc(&base, (int64_t)workspace_layout(p, kWsAll, nullptr, nullptr)));
+        p->ws_base = base;
+        workspace_layout(p, kWsAll, base, &p->ws);
+    }
     chk(dalloc(&p->a_ptr, (int64_t)aptr.size()));
     chk(dalloc(&p->a_vox, (int64_t)avox.size()));
     chk(dalloc(&p->a_fas, (int64_t)afas.size()));
@@ -1651,76 +1690,126 @@ extern "C" life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int1
 
 static bool need(const void *ptr, int64_t n) { return n == 0 || ptr != nullptr; }
 
-extern "C" life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream)
+namespace {
+
+// The workspace of a call: the caller's scratch (at least life_plan_scratch_bytes,
+// 256-byte aligned) carved like the plan's own, or the plan's own when scratch is NULL.
+life_status call_workspace(life_plan_s *p, void *scratch, uint64_t bytes, Workspace *ws)
 {
-    if (!plan) return LIFE_EINVAL;
-    const life_dims &d = plan->dims;
-    if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(w, d.n_fascicles) ||
-        !need(y, (int64_t)d.n_theta * d.n_voxels))
-        return LIFE_EINVAL;
-    DeviceGuard g(plan->device);
-    if (!g.ok) return LIFE_EDEVICE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    life_status st = enqueue_gather(plan, w, s);
-    if (st != LIFE_OK) return st;
-    return enqueue_dsc(plan, D, plan->w_rank, nullptr, y, nullptr, s);
+    if (!scratch) {
+        *ws = p->ws;
+        return LIFE_OK;
+    }
+    const size_t want = workspace_layout(p, kWsAll, nullptr, nullptr);
+    if (bytes < want || (reinterpret_cast<uintptr_t>(scratch) & 255) != 0) return LIFE_EINVAL;
+    workspace_layout(p, kWsAll, static_cast<char *>(scratch), ws);
+    return LIFE_OK;
 }
 
-extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream)
+life_status dsc_call(life_plan_s *plan, const Workspace &ws, const float *D, const float *w, float *y,
+                     hipStream_t s)
+{
+    life_status st = enqueue_gather(plan, ws, w, s);
+    if (st != LIFE_OK) return st;
+    return enqueue_dsc(plan, D, ws.w_rank, nullptr, y, nullptr, s);
+}
+
+bool dsc_args_ok(const life_plan_s *plan, const float *D, const float *w, const float *y)
+{
+    const life_dims &d = plan->dims;
+    return need(D, (int64_t)d.n_theta * d.n_atoms) && need(w, d.n_fascicles) && need(y, (int64_t)d.n_theta * d.n_voxels);
+}
+
+}  // namespace
+
+extern "C" life_status life_plan_scratch_bytes(life_plan_t plan, uint64_t *bytes)
+{
+    if (!plan || !bytes) return LIFE_EINVAL;
+    *bytes = workspace_layout(plan, kWsAll, nullptr, nullptr);
+    return LIFE_OK;
+}
+
+extern "C" life_status life_dsc_ws(life_plan_t plan, const float *D, const float *w, float *y, void *scratch,
+                                   uint64_t scratch_bytes, void *stream)
+{
+    if (!plan || !dsc_args_ok(plan, D, w, y)) return LIFE_EINVAL;
+    Workspace ws;
+    life_status st = call_workspace(plan, scratch, scratch_bytes, &ws);
+    if (st != LIFE_OK) return st;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return LIFE_EDEVICE;
+    return dsc_call(plan, ws, D, w, y, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream)
+{
+    return life_dsc_ws(plan, D, w, y, nullptr, 0, stream);
+}
+
+extern "C" life_status life_wc_ws(life_plan_t plan, const float *D, const float *y, float *g, void *scratch,
+                                  uint64_t scratch_bytes, void *stream)
 {
     if (!plan) return LIFE_EINVAL;
     const life_dims &d = plan->dims;
     if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(y, (int64_t)d.n_theta * d.n_voxels) ||
         !need(g, d.n_fascicles))
         return LIFE_EINVAL;
+    Workspace ws;
+    life_status st = call_workspace(plan, scratch, scratch_bytes, &ws);
+    if (st != LIFE_OK) return st;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_wc(plan, D, y, g, plan->fas_ext, nullptr, Gate{nullptr, 0}, static_cast<hipStream_t>(stream));
+    return enqueue_wc(plan, ws, D, y, g, plan->fas_ext, nullptr, Gate{nullptr, 0}, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream)
+{
+    return life_wc_ws(plan, D, y, g, nullptr, 0, stream);
 }
 
 namespace {
 
 // One SBB-NNLS iteration; gt_prev != NULL selects the lagged (eqs. 7-8) step.
-life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float *w, float *gt_prev,
-                        life_sbb_state *state, hipStream_t s)
+life_status enqueue_sbb(life_plan_s *plan, const Workspace &ws, const float *D, const float *b, float *w,
+                        float *gt_prev, life_sbb_state *state, hipStream_t s)
 {
     const life_dims &d = plan->dims;
     const bool lagged = gt_prev != nullptr;
     const int64_t ps = plan->part_stride;
-    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps, *p_vpp = plan->part + 3 * ps;
-    double *p_q = plan->part + 4 * ps;
+    double *p_r = ws.part, *p_gt = ws.part + ps, *p_vp = ws.part + 2 * ps, *p_vpp = ws.part + 3 * ps;
+    double *p_q = ws.part + 4 * ps;
     const int nv = d.n_voxels, nf = d.n_fascicles;
     const int nb_dsc = nv > 0 ? dsc_partials(plan) : 0;
     const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
     const int nb_sum = nf > 0 ? cdiv(nf, kFasPerBlock) : 0;
     life_status st;
     // weights into fascicle-rank order (every vector of the step below stays in it)
-    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
+    if ((st = enqueue_gather(plan, ws, w, s)) != LIFE_OK) return st;
     // r = M w - b, partial ||r||^2
-    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, ws.w_rank, b, ws.r, p_r, s)) != LIFE_OK) return st;
     // g = M^T r
-    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, ws, D, ws.r, ws.g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
     // g~ and ||g~||^2
     if (nf > 0) {
         st = launch(plan, LIFE_K_MASK, s, [&] {
-            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
+            k_mask<<<nb_mask, kBlock, 0, s>>>(ws.w_rank, ws.g, ws.gt, p_gt, nf);
         });
         if (st != LIFE_OK) return st;
     }
     // q: g~ (Algorithm 1) or the previous iterate's g~ (eqs. 7-8), and ||q||^2
-    const float *q = plan->gt;
+    const float *q = ws.gt;
     if (lagged && nf > 0) {
         st = launch(plan, LIFE_K_MASK, s, [&] {
-            k_lag_q<<<nb_mask, kBlock, 0, s>>>(gt_prev, plan->fas_ext, plan->gt, plan->q, p_q, state, nf);
+            k_lag_q<<<nb_mask, kBlock, 0, s>>>(gt_prev, plan->fas_ext, ws.gt, ws.q, p_q, state, nf);
         });
         if (st != LIFE_OK) return st;
-        q = plan->q;
+        q = ws.q;
     }
     // v' = M q, ||v'||^2
-    if ((st = enqueue_dsc(plan, D, q, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, q, nullptr, ws.vp, p_vp, s)) != LIFE_OK) return st;
     // v'' = M^T v', ||v''||^2, on the iterations of the second alpha form (even i
     // in Algorithm 1, odd i in eqs. 7-8); the kernels test the parity on the device
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, p_vpp, Gate{state, lagged ? 1 : 0}, s, false)) !=
+    if ((st = enqueue_wc(plan, ws, D, ws.vp, ws.vpp, nullptr, p_vpp, Gate{state, lagged ? 1 : 0}, s, false)) !=
         LIFE_OK)
         return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
@@ -1730,7 +1819,7 @@ life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float
     if (st != LIFE_OK) return st;
     if (nf > 0) {
         st = launch(plan, LIFE_K_UPDATE, s, [&] {
-            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, state,
+            k_update<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, ws.w_rank, ws.gt, plan->fas_ext, state,
                                                          lagged ? gt_prev : nullptr, nf);
         });
     }
@@ -1742,36 +1831,36 @@ life_status enqueue_sbb(life_plan_s *plan, const float *D, const float *b, float
 namespace {
 
 // One SBB-NNLS iteration (Algorithm 1) of every instance of a batched plan.
-life_status enqueue_sbb_batch(life_plan_s *plan, const float *D, const float *b, float *w, life_sbb_state *states,
-                              hipStream_t s)
+life_status enqueue_sbb_batch(life_plan_s *plan, const Workspace &ws, const float *D, const float *b, float *w,
+                              life_sbb_state *states, hipStream_t s)
 {
     const life_dims &d = plan->dims;
     const int64_t ps = plan->part_stride;
-    double *p_r = plan->part, *p_gt = plan->part + ps, *p_vp = plan->part + 2 * ps;
+    double *p_r = ws.part, *p_gt = ws.part + ps, *p_vp = ws.part + 2 * ps;
     const int nf = d.n_fascicles;
     const int nb_mask = nf > 0 ? cdiv(nf, kBlock) : 0;
     life_status st;
-    if ((st = enqueue_gather(plan, w, s)) != LIFE_OK) return st;
-    if ((st = enqueue_dsc(plan, D, plan->w_rank, b, plan->r, p_r, s)) != LIFE_OK) return st;
-    if ((st = enqueue_wc(plan, D, plan->r, plan->g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
+    if ((st = enqueue_gather(plan, ws, w, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, ws.w_rank, b, ws.r, p_r, s)) != LIFE_OK) return st;
+    if ((st = enqueue_wc(plan, ws, D, ws.r, ws.g, nullptr, nullptr, Gate{nullptr, 0}, s)) != LIFE_OK) return st;
     if (nf > 0) {
         st = launch(plan, LIFE_K_MASK, s, [&] {
-            k_mask<<<nb_mask, kBlock, 0, s>>>(plan->w_rank, plan->g, plan->gt, p_gt, nf);
+            k_mask<<<nb_mask, kBlock, 0, s>>>(ws.w_rank, ws.g, ws.gt, p_gt, nf);
         });
         if (st != LIFE_OK) return st;
     }
-    if ((st = enqueue_dsc(plan, D, plan->gt, nullptr, plan->vp, p_vp, s)) != LIFE_OK) return st;
+    if ((st = enqueue_dsc(plan, D, ws.gt, nullptr, ws.vp, p_vp, s)) != LIFE_OK) return st;
     // instances advance together: the first instance's parity gates the second WC
-    if ((st = enqueue_wc(plan, D, plan->vp, plan->vpp, nullptr, nullptr, Gate{states, 0}, s, false)) != LIFE_OK)
+    if ((st = enqueue_wc(plan, ws, D, ws.vp, ws.vpp, nullptr, nullptr, Gate{states, 0}, s, false)) != LIFE_OK)
         return st;
     st = launch(plan, LIFE_K_ALPHA, s, [&] {
-        k_alpha_batch<<<plan->n_inst, kAlphaThreads, 0, s>>>(p_r, p_vp, plan->inst_chunk, plan->gt, plan->vpp,
+        k_alpha_batch<<<plan->n_inst, kAlphaThreads, 0, s>>>(p_r, p_vp, plan->inst_chunk, ws.gt, ws.vpp,
                                                              plan->inst_rank, states);
     });
     if (st != LIFE_OK) return st;
     if (nf > 0) {
         st = launch(plan, LIFE_K_UPDATE, s, [&] {
-            k_update_batch<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, plan->w_rank, plan->gt, plan->fas_ext, states,
+            k_update_batch<<<cdiv(nf, kBlock), kBlock, 0, s>>>(w, ws.w_rank, ws.gt, plan->fas_ext, states,
                                                                plan->inst_rank, plan->n_inst, nf);
         });
     }
@@ -1817,9 +1906,10 @@ extern "C" life_status life_plan_tune(life_plan_t plan, const float *D, const fl
     for (int pol : pols) {
         if (install(pol) != hipSuccess) { st = LIFE_EDEVICE; break; }
         auto run = [&]() {
-            if (enqueue_gather(plan, w, nullptr) != LIFE_OK) return false;
-            if (enqueue_dsc(plan, D, plan->w_rank, nullptr, plan->r, nullptr, nullptr) != LIFE_OK) return false;
-            return enqueue_wc(plan, D, y, plan->g, nullptr, nullptr, Gate{nullptr, 0}, nullptr) == LIFE_OK;
+            const Workspace &ws = plan->ws;
+            if (enqueue_gather(plan, ws, w, nullptr) != LIFE_OK) return false;
+            if (enqueue_dsc(plan, D, ws.w_rank, nullptr, ws.r, nullptr, nullptr) != LIFE_OK) return false;
+            return enqueue_wc(plan, ws, D, y, ws.g, nullptr, nullptr, Gate{nullptr, 0}, nullptr) == LIFE_OK;
         };
         if (!run()) { st = LIFE_EDEVICE; break; }                 // warm-up
         float ms = 0.f;
@@ -1860,20 +1950,30 @@ extern "C" life_status life_sbbnnls_step_batch(life_plan_t plan, const float *D,
     if (!chunked(plan)) return life_sbbnnls_step(plan, D, b, w, states, stream);   // one instance
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_sbb_batch(plan, D, b, w, states, static_cast<hipStream_t>(stream));
+    return enqueue_sbb_batch(plan, plan->ws, D, b, w, states, static_cast<hipStream_t>(stream));
 }
 
-extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
-                                         life_sbb_state *state, void *stream)
+extern "C" life_status life_sbbnnls_step_ws(life_plan_t plan, const float *D, const float *b, float *w,
+                                            life_sbb_state *state, void *scratch, uint64_t scratch_bytes,
+                                            void *stream)
 {
     if (!plan || !state) return LIFE_EINVAL;
     const life_dims &d = plan->dims;
     if (!need(D, (int64_t)d.n_theta * d.n_atoms) || !need(b, (int64_t)d.n_theta * d.n_voxels) ||
         !need(w, d.n_fascicles))
         return LIFE_EINVAL;
+    Workspace ws;
+    life_status st = call_workspace(plan, scratch, scratch_bytes, &ws);
+    if (st != LIFE_OK) return st;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_sbb(plan, D, b, w, nullptr, state, static_cast<hipStream_t>(stream));
+    return enqueue_sbb(plan, ws, D, b, w, nullptr, state, static_cast<hipStream_t>(stream));
+}
+
+extern "C" life_status life_sbbnnls_step(life_plan_t plan, const float *D, const float *b, float *w,
+                                         life_sbb_state *state, void *stream)
+{
+    return life_sbbnnls_step_ws(plan, D, b, w, state, nullptr, 0, stream);
 }
 
 extern "C" life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D, const float *b, float *w,
@@ -1886,7 +1986,7 @@ extern "C" life_status life_sbbnnls_step_lagged(life_plan_t plan, const float *D
         return LIFE_EINVAL;
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
-    return enqueue_sbb(plan, D, b, w, gt_prev, state, static_cast<hipStream_t>(stream));
+    return enqueue_sbb(plan, plan->ws, D, b, w, gt_prev, state, static_cast<hipStream_t>(stream));
 }
 
 extern "C" life_status life_dict_grad(life_plan_t plan, const float *w, const float *ybar, float *dD, void *stream)
@@ -1899,9 +1999,10 @@ extern "C" life_status life_dict_grad(life_plan_t plan, const float *w, const fl
     DeviceGuard gd(plan->device);
     if (!gd.ok) return LIFE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    life_status st = enqueue_gather(plan, w, s);
+    const Workspace &ws = plan->ws;
+    life_status st = enqueue_gather(plan, ws, w, s);
     if (st != LIFE_OK) return st;
-    return enqueue_dd(plan, ybar, dD, s);
+    return enqueue_dd(plan, ws, ybar, dD, s);
 }
 
 extern "C" life_status life_profile_enable(life_plan_t plan, int enable)

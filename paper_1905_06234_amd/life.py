@@ -61,6 +61,10 @@ _SIGS = {
     "life_dsc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_wc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_sbbnnls_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "life_plan_scratch_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    "life_dsc_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
+    "life_wc_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
+    "life_sbbnnls_step_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
     "life_sbbnnls_step_lagged": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "life_dict_grad": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -304,22 +308,47 @@ class Plan:
     def _d(self, D):
         return _dev_f32(D, self.dims.n_theta * self.dims.n_atoms, "D")
 
-    def dsc(self, D, w, y=None, stream=None):
-        """y = M w (life_dsc)."""
+    def scratch_bytes(self) -> int:
+        """Bytes of caller scratch the *_ws calls need (life_plan_scratch_bytes)."""
+        n = ctypes.c_uint64()
+        _check("life_plan_scratch_bytes", load().life_plan_scratch_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def new_scratch(self, device=None):
+        """A device buffer for the scratch argument of dsc / wc / sbbnnls_step."""
+        torch = _torch()
+        return torch.empty(self.scratch_bytes(), dtype=torch.uint8, device=device or "cuda")
+
+    @staticmethod
+    def _scratch(scratch):
+        torch = _torch()
+        if not (isinstance(scratch, torch.Tensor) and scratch.is_cuda and scratch.dtype == torch.uint8
+                and scratch.is_contiguous()):
+            raise ValueError("scratch must be a contiguous uint8 device tensor (see new_scratch)")
+        return ctypes.c_void_p(scratch.data_ptr()), ctypes.c_uint64(scratch.numel())
+
+    def dsc(self, D, w, y=None, stream=None, scratch=None):
+        """y = M w (life_dsc; life_dsc_ws with a caller scratch buffer)."""
         torch = _torch()
         if y is None:
             y = torch.empty(self.n_signal, dtype=torch.float32, device=w.device)
-        _check("life_dsc", load().life_dsc(self._h, self._d(D), _dev_f32(w, self.dims.n_fascicles, "w"),
-                                           _dev_f32(y, self.n_signal, "y"), _stream(stream, w.device)))
+        args = (self._h, self._d(D), _dev_f32(w, self.dims.n_fascicles, "w"), _dev_f32(y, self.n_signal, "y"))
+        if scratch is None:
+            _check("life_dsc", load().life_dsc(*args, _stream(stream, w.device)))
+        else:
+            _check("life_dsc_ws", load().life_dsc_ws(*args, *self._scratch(scratch), _stream(stream, w.device)))
         return y
 
-    def wc(self, D, y, g=None, stream=None):
-        """g = M^T y (life_wc)."""
+    def wc(self, D, y, g=None, stream=None, scratch=None):
+        """g = M^T y (life_wc; life_wc_ws with a caller scratch buffer)."""
         torch = _torch()
         if g is None:
             g = torch.empty(self.dims.n_fascicles, dtype=torch.float32, device=y.device)
-        _check("life_wc", load().life_wc(self._h, self._d(D), _dev_f32(y, self.n_signal, "y"),
-                                         _dev_f32(g, self.dims.n_fascicles, "g"), _stream(stream, y.device)))
+        args = (self._h, self._d(D), _dev_f32(y, self.n_signal, "y"), _dev_f32(g, self.dims.n_fascicles, "g"))
+        if scratch is None:
+            _check("life_wc", load().life_wc(*args, _stream(stream, y.device)))
+        else:
+            _check("life_wc_ws", load().life_wc_ws(*args, *self._scratch(scratch), _stream(stream, y.device)))
         return g
 
     def dict_grad(self, w, ybar, dD=None, stream=None):
@@ -342,12 +371,16 @@ class Plan:
             raise ValueError("state must be a 48-byte contiguous device tensor (see new_state)")
         return ctypes.c_void_p(state.data_ptr())
 
-    def sbbnnls_step(self, D, b, w, state, stream=None):
-        """One SBB-NNLS iteration (Algorithm 1) in place on w; state from new_state()."""
-        st = self._state(state)
-        _check("life_sbbnnls_step",
-               load().life_sbbnnls_step(self._h, self._d(D), _dev_f32(b, self.n_signal, "b"),
-                                        _dev_f32(w, self.dims.n_fascicles, "w"), st, _stream(stream, w.device)))
+    def sbbnnls_step(self, D, b, w, state, stream=None, scratch=None):
+        """One SBB-NNLS iteration (Algorithm 1) in place on w; state from new_state()
+        (life_sbbnnls_step; life_sbbnnls_step_ws with a caller scratch buffer)."""
+        args = (self._h, self._d(D), _dev_f32(b, self.n_signal, "b"), _dev_f32(w, self.dims.n_fascicles, "w"),
+                self._state(state))
+        if scratch is None:
+            _check("life_sbbnnls_step", load().life_sbbnnls_step(*args, _stream(stream, w.device)))
+        else:
+            _check("life_sbbnnls_step_ws",
+                   load().life_sbbnnls_step_ws(*args, *self._scratch(scratch), _stream(stream, w.device)))
         return w
 
     def sbbnnls_step_lagged(self, D, b, w, gt_prev, state, stream=None):
