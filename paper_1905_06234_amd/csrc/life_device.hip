@@ -197,13 +197,19 @@ struct WaveRange {
 
 // DSC: y[:, v] = sum_{c in seg(v)} D[:, atom_c] * (phi_c * w[fas_c])   (minus b[:, v] if bsub)
 // NC = 32-float chunks per LDS row (N_theta <= 32 NC).
+// The weights of the chunk's fascicles are first gathered into LDS (wl, after the
+// dictionary tile: one value per distinct fascicle of the chunk, in rank order, so
+// the gather reads ascending addresses), and every nonzero reads its weight there
+// through its local index.
 template <int NC>
 __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_map,
                                                    const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
                                                    const int16_t *__restrict__ atom,
-                                                   const int32_t *__restrict__ fas,
+                                                   const uint16_t *__restrict__ loc,
                                                    const float *__restrict__ phi,
+                                                   const int32_t *__restrict__ cfas_ptr,
+                                                   const int32_t *__restrict__ cfas,
                                                    const float *__restrict__ w,
                                                    const float *__restrict__ D,
                                                    const float *__restrict__ bsub,
@@ -217,6 +223,11 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float *wl = lds + TA * ROW;
+    {
+        const int f0 = cfas_ptr[chunk], nl = cfas_ptr[chunk + 1] - f0;
+        for (int i = threadIdx.x; i < nl; i += kWG) wl[i] = w[cfas[f0 + i]];
+    }   // visible after the first barrier of the tile loop
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
@@ -236,26 +247,26 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         // w gather of batch i+1 are in flight while batch i is computed
         int bq = R.next(R.p[0]);
         int ix = R.entry(R.p[0], mypos);
-        int a_0 = atom[ix], f_0 = fas[ix];
+        int a_0 = atom[ix], f_0 = loc[ix];
         float ph_0 = phi[ix];
         ix = R.entry(bq, mypos);
-        int a_1 = atom[ix], f_1 = fas[ix];
+        int a_1 = atom[ix], f_1 = loc[ix];
         float ph_1 = phi[ix];
-        float w_0 = w[f_0];
+        float w_0 = wl[f_0];
 #pragma unroll
         for (int j = 0; j < kWaveVoxels; ++j) {
             for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
                 const int m = min(kBatch, R.p[j + 1] - b);
                 const int a_c = a_0;
                 const float ph_c = ph_0, w_c = w_0;
-                const float w_1 = w[f_1];
+                const float w_1 = wl[f_1];
                 bq = R.next(bq);
                 ix = R.entry(bq, mypos);
                 a_0 = a_1;
                 ph_0 = ph_1;
                 w_0 = w_1;
                 a_1 = atom[ix];
-                f_1 = fas[ix];
+                f_1 = loc[ix];
                 ph_1 = phi[ix];
                 const bool valid = mypos < m;
                 const int aoff = valid ? (a_c - a0) * ROW : 0;
@@ -324,43 +335,57 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
 // ----------------------------------------------------------------------------- WC pass 1 on the matrix cores
 // For one chunk and one atom tile every needed projection <D[:, a], y[:, v]> is an
 // entry of the dense block P = D_tile^T Y_chunk (atoms x 64 voxel slots), formed on
-// v_mfma_f32_32x32x16_f16; each nonzero then costs one LDS lookup,
-// z_c = phi_c P[atom_c][slot_c], instead of an N_theta-long dot product.
-// FP32 operands enter the matrix cores as FP16 pairs: a column is scaled by a power
-// of two 2^k that puts its largest magnitude in [2^13, 2^14), and each scaled value
-// x becomes hi = fp16(x), lo = fp16(x - hi), so x = hi + lo up to 2^-22 |x| (for
-// values so small that lo is subnormal, up to 2^-38 of the column maximum).
-// The product takes hi*hi + (hi*lo + lo*hi) with FP32 accumulation (the dropped
-// lo*lo term is below 2^-22 relative), and the scales (per atom for D, per voxel
-// slot for y) are undone exactly on P.  Every element of P depends only on its own
-// atom column and voxel column, so results do not depend on the chunking.
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+// v_mfma_i32_32x32x32_i8; each nonzero then costs one LDS lookup.
+// Exact integer products: a column (an atom of D, a voxel slot of y) is scaled by
+// a power of two 2^k that puts its largest magnitude in [2^29, 2^30) and rounded
+// to an integer q (|q| <= 2^30, to 2^-31 of the column maximum), written as four
+// balanced 8-bit digits q = q3 2^24 + q2 2^16 + q1 2^8 + q0 (q0..q2 in [-128, 127],
+// |q3| <= 64).  The matrix cores sum the digit products exactly in 32-bit
+// integers, grouped by weight: C6 = S33, C5 = S32 + S23, C4 = S31 + S22 + S13,
+// C3 = S30 + S21 + S12 + S03 (S_ij = sum over theta of digit i of D times digit j
+// of y); the terms of weight 2^16 and below are dropped (about 2^-30 of the
+// largest possible product sum, and symmetric about zero).  Then
+// P = (2^24 C6 + 2^16 C5 + 2^8 C4 + C3) 2^(24 - k_a - k_v), formed exactly in
+// double and rounded once to float: no accumulation bias (FP32 accumulation on the
+// matrix cores rounds toward zero), and about 2^-24 relative error per projection.
+// Every element of P depends only on its own atom column and voxel column, so
+// results do not depend on the chunking.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kPS = 64;   // LDS row stride of P (floats): one row per atom, one column per slot
+constexpr int kPS = 64;     // LDS row stride of P (floats): one row per atom, one column per slot
+constexpr int kQ8Pad = 16;  // bytes after each slot's digits in LDS (spreads the banks)
+constexpr int kDigits = 4;
 
-// exponent k with m 2^k in [2^13, 2^14) (0 when m is zero or not finite), clamped so
-// that 2^-k stays a normal float
-__device__ __forceinline__ int split_exp(float m)
+// exponent k with m 2^k in [2^29, 2^30) (0 when m is zero or not finite), clamped so
+// that 2^(24-k) and 2^-k stay normal floats
+__device__ __forceinline__ int q30_exp(float m)
 {
     if (!(m > 0.f) || !(m <= 3.4028234e38f)) return 0;
     int e;
     (void)frexpf(m, &e);
-    return min(120, max(-120, 14 - e));
+    return min(100, max(-100, 30 - e));
 }
 
-__device__ __forceinline__ void split_f16(float x, _Float16 &hi, _Float16 &lo)
+// balanced base-256 digits of the integer nearest x (|x| <= 2^30)
+__device__ __forceinline__ void q30_digits(float x, int8_t *d, int stride)
 {
-    hi = (_Float16)x;
-    lo = (_Float16)(x - (float)hi);   // x - hi is exact in FP32
+    int q = (int)rintf(x);
+#pragma unroll
+    for (int g = 0; g < kDigits - 1; ++g) {
+        const int dg = ((q + 128) & 255) - 128;
+        d[g * stride] = (int8_t)dg;
+        q = (q - dg) >> 8;
+    }
+    d[(kDigits - 1) * stride] = (int8_t)q;
 }
 
 // A operands of P = D_tile^T Y: one wave per (tile t, atom block ab of 32, row r);
-// for a = t TA + 32 ab + r and theta = 16 ks + 8 hf + i, half i of
-// frag[(((t AB + ab) KS + ks) 2 + part) 64 + 32 hf + r] is part 0 (hi) or 1 (lo) of
+// for a = t TA + 32 ab + r and theta = 32 ks + 16 hf + i, byte i of
+// frag[(((t AB + ab) KS + ks) kDigits + g) 64 + 32 hf + r] is digit g of
 // 2^{k_a} D[theta][a] (zero outside the tile, the dictionary or N_theta), and
-// dscale[(t AB + ab) 32 + r] = 2^{-k_a}.  N_theta <= 128.
-__global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D, h8 *__restrict__ frag,
+// dscale[(t AB + ab) 32 + r] = 2^{24 - k_a}.  N_theta <= 128 (KS <= 4).
+__global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D, i32x4 *__restrict__ frag,
                                                       float *__restrict__ dscale, int nth, int na, int T, int TA,
                                                       int AB, int KS, Gate gate)
 {
@@ -376,61 +401,53 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
     float m = fmaxf(fabsf(x0), fabsf(x1));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    const int e = split_exp(m);
-    if (lane == 0) dscale[i] = ldexpf(1.f, -e);
-    _Float16 *f = reinterpret_cast<_Float16 *>(frag);
+    const int e = q30_exp(m);
+    if (lane == 0) dscale[i] = ldexpf(1.f, 24 - e);
+    int8_t *f = reinterpret_cast<int8_t *>(frag);
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
         const int th = lane + 64 * hh;
-        if (th < 16 * KS) {
-            const int ks = th / 16, hf = (th % 16) / 8, q = th % 8;
-            const size_t base = ((size_t)((t * AB + ab) * KS + ks) * 2 * 64 + 32 * hf + r) * 8 + q;
-            _Float16 hi, lo;
-            split_f16(ldexpf(hh ? x1 : x0, e), hi, lo);
-            f[base] = hi;
-            f[base + 64 * 8] = lo;
+        if (th < 32 * KS) {
+            const int ks = th / 32, hf = (th % 32) / 16, q = th % 16;
+            const size_t base = ((size_t)((t * AB + ab) * KS + ks) * kDigits * 64 + 32 * hf + r) * 16 + q;
+            q30_digits(ldexpf(hh ? x1 : x0, e), f + base, 64 * 16);
         }
     }
 }
 
-// WC pass 1: z[z_pos[q]] = phi_q * <D[:, atom_q], y[:, v]> for every real entry q of
-// the chunked layout (pads are skipped: pass 2 never reads them).  z_pos keeps each
-// chunk's values inside the chunk's own range, grouped by tile and in WC order
-// inside a tile, so pass 2 reads one fascicle's values in a chunk as short
-// contiguous runs, and one tile's values fill the sub-range
-// [tile_z[2 i], tile_z[2 i] + tile_z[2 i + 1]) of i = chunk T + t.
+// WC pass 1: one value per run of one fascicle's nonzeros in one (chunk, tile):
+// zrun[r] = sum over the run's entries e of phi_e * <D[:, atom_e], y[:, v_e]>.
+// Per tile, waves 0..AB-1 first form P = D_tile^T Y_chunk in LDS (one 32-atom block
+// each, both 32-slot halves); then every wave walks its own entry range of the
+// (chunk, tile) bucket (cut at run starts) in batches of 64 consecutive entries,
+// the next batch in flight: each lane looks up its entry's projection in P, and a
+// segmented scan over the batch (Hillis-Steele with run-start flags, fixed order)
+// sums each run; the lane at a run's end writes it, a run that crosses into the
+// next batch carries its partial sum there.
 // LDS: P [32 AB][kPS] floats, Y hi and lo [64 slots][YS] halves (YS = 16 KS + 8:
-// conflict-free 16-byte reads along theta), the 64 slot scales, then cap floats
-// that stage the first cap values of the tile's sub-range.  Waves 0..AB-1 each form
-// one 32-atom block of P for both 32-slot halves; then every wave looks up its own
-// slots' nonzeros and puts each value in the stage (or, beyond cap, straight into
-// z); the stage then goes out as one coalesced stream.
-__global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ chunk_map,
+// conflict-free 16-byte reads along theta), the 64 slot scales.
+__global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ chunk_map,
                                                   const int32_t *__restrict__ chunk_vox,
-                                                  const int32_t *__restrict__ wave_work,
-                                                  const int16_t *__restrict__ atom,
-                                                  const float *__restrict__ phi,
-                                                  const int32_t *__restrict__ z_pos,
-                                                  const int32_t *__restrict__ tile_z,
-                                                  const h8 *__restrict__ frag,
+                                                  const uint16_t *__restrict__ wkey,
+                                                  const float *__restrict__ wphi,
+                                                  const int32_t *__restrict__ wc_wave,
+                                                  const int32_t *__restrict__ wc_wrun,
+                                                  const i32x4 *__restrict__ frag,
                                                   const float *__restrict__ dscale,
                                                   const float *__restrict__ y,
-                                                  float *__restrict__ z, int nth, int T, int TA, int AB,
-                                                  int KS, int cap, Gate gate)
+                                                  float *__restrict__ zrun, int nth, int T, int AB, int KS, Gate gate)
 {
     if (gated_off(gate)) return;   // uniform over the grid
     extern __shared__ float4 lds4[];
     float *P = reinterpret_cast<float *>(lds4);
-    const int YS = 16 * KS + 8;
-    _Float16 *Yh = reinterpret_cast<_Float16 *>(P + AB * 32 * kPS);
-    _Float16 *Yl = Yh + kChunkVoxels * YS;
-    float *yscale = reinterpret_cast<float *>(Yl + kChunkVoxels * YS);
-    float *stage = yscale + kChunkVoxels;
+    const int YS = 32 * KS + kQ8Pad;   // bytes per slot and digit
+    int8_t *Yq = reinterpret_cast<int8_t *>(P + AB * 32 * kPS);   // [kDigits][64 slots][YS]
+    float *yscale = reinterpret_cast<float *>(Yq + kDigits * kChunkVoxels * YS);
     const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // the chunk's y columns, each scaled by its own power of two and split
+    // the chunk's y columns, each scaled by its own power of two and cut into digits
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
         const int slot = wave * kWaveVoxels + j;
@@ -443,78 +460,97 @@ __global__ __launch_bounds__(kWG) void k_wcz_mfma(const int32_t *__restrict__ ch
         float m = fmaxf(fabsf(x0), fabsf(x1));
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-        const int e = split_exp(m);
+        const int e = q30_exp(m);
         if (lane == 0) yscale[slot] = ldexpf(1.f, -e);
-        if (lane < 16 * KS) split_f16(ldexpf(x0, e), Yh[slot * YS + lane], Yl[slot * YS + lane]);
-        if (lane + 64 < 16 * KS) split_f16(ldexpf(x1, e), Yh[slot * YS + lane + 64], Yl[slot * YS + lane + 64]);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int th = lane + 64 * hh;
+            if (th < 32 * KS) q30_digits(ldexpf(hh ? x1 : x0, e), Yq + slot * YS + th, kChunkVoxels * YS);
+        }
     }
 
     for (int t = 0; t < T; ++t) {
-        const int a0 = t * TA;
         __syncthreads();   // Y is staged / the previous tile's lookups are done with P
         if (wave < AB) {
-            // hi*hi and the two correction products accumulate separately: the matrix
-            // cores' FP32 accumulation is biased toward zero by about 2^-24 of each
-            // partial sum, and a bias on the large hi*hi sums would add up coherently in
-            // sums over many fascicles (<w, M^T y> drifts by ~1e-5 of itself otherwise)
-            f32x16 c0 = {}, c1 = {}, e0 = {}, e1 = {};
-            const h8 *fa = frag + (size_t)(t * AB + wave) * KS * 2 * 64 + lane;
-            const int col = lane & 31, kh = 8 * (lane >> 5);
-            for (int ks = 0; ks < KS; ++ks) {
-                const h8 ah = fa[(2 * ks) * 64], al = fa[(2 * ks + 1) * 64];
-                const int k0 = 16 * ks + kh;
-                const h8 bh0 = *reinterpret_cast<const h8 *>(Yh + col * YS + k0);
-                const h8 bh1 = *reinterpret_cast<const h8 *>(Yh + (32 + col) * YS + k0);
-                const h8 bl0 = *reinterpret_cast<const h8 *>(Yl + col * YS + k0);
-                const h8 bl1 = *reinterpret_cast<const h8 *>(Yl + (32 + col) * YS + k0);
-                c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh0, c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh1, c1, 0, 0, 0);
-                e0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl0, e0, 0, 0, 0);
-                e1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl1, e1, 0, 0, 0);
-                e0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh0, e0, 0, 0, 0);
-                e1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh1, e1, 0, 0, 0);
-            }
-            // accumulator r of lane l holds (atom row 8 (r/4) + 4 (l/32) + r%4, slot l%32)
-            const float s0 = yscale[col], s1 = yscale[32 + col];
+            // the A digits come from L2 once per slot half (held for both halves they
+            // would not fit the registers beside the accumulators)
+            const i32x4 *fa = frag + (size_t)(t * AB + wave) * KS * kDigits * 64 + lane;
+            const int col = lane & 31, kh = 16 * (lane >> 5);
             const float *ds = dscale + (size_t)(t * AB + wave) * 32;
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                i32x16 c6 = {}, c5 = {}, c4 = {}, c3 = {};
+                const int8_t *yb = Yq + (32 * h + col) * YS + kh;
+                for (int ks = 0; ks < KS; ++ks) {
+                    i32x4 a[kDigits];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                const float d = ds[row];
-                P[(32 * wave + row) * kPS + col] = ((c0[r] + e0[r]) * d) * s0;
-                P[(32 * wave + row) * kPS + 32 + col] = ((c1[r] + e1[r]) * d) * s1;
-            }
-        }
-        __syncthreads();
-        const WaveRange R(wave_work, chunk, t, T, wave);
-        const int p1 = R.p[1], p2 = R.p[2], p3 = R.p[3], pe = R.p[kWaveVoxels];
-        const int zbeg = uni(tile_z[2 * (chunk * T + t)]), zcnt = uni(tile_z[2 * (chunk * T + t) + 1]);
-        for (int b = R.p[0]; b < pe; b += 4 * 64) {
-            int aa[4], zz[4];
-            float ff[4];
+                    for (int g = 0; g < kDigits; ++g) a[g] = fa[(ks * kDigits + g) * 64];
+                    // one B digit at a time (fewer live registers): digit j meets A digits
+                    // i >= 3 - j, and the product goes to the class of weight i + j
+                    const int8_t *yk = yb + 32 * ks;
+                    i32x4 b = *reinterpret_cast<const i32x4 *>(yk + 3 * kChunkVoxels * YS);
+                    c6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c6, 0, 0, 0);
+                    c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c5, 0, 0, 0);
+                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c4, 0, 0, 0);
+                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b, c3, 0, 0, 0);
+                    b = *reinterpret_cast<const i32x4 *>(yk + 2 * kChunkVoxels * YS);
+                    c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c5, 0, 0, 0);
+                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c4, 0, 0, 0);
+                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c3, 0, 0, 0);
+                    b = *reinterpret_cast<const i32x4 *>(yk + kChunkVoxels * YS);
+                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c4, 0, 0, 0);
+                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c3, 0, 0, 0);
+                    b = *reinterpret_cast<const i32x4 *>(yk);
+                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c3, 0, 0, 0);
+                }
+                // accumulator r of lane l holds (atom row 8 (r/4) + 4 (l/32) + r%4, slot 32 h + l%32)
+                const float sv = yscale[32 * h + col];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = b + 64 * u + lane;
-                const int ix = idx < pe ? idx : R.p[0];
-                aa[u] = atom[ix];
-                ff[u] = phi[ix];
-                zz[u] = z_pos[ix];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = b + 64 * u + lane;
-                const int loc = zz[u] - zbeg;
-                if (idx < pe && (unsigned)loc < (unsigned)zcnt) {
-                    const int slot = wave * kWaveVoxels + (idx >= p1) + (idx >= p2) + (idx >= p3);
-                    const float v = ff[u] * P[(aa[u] - a0) * kPS + slot];
-                    if (loc < cap) stage[loc] = v;
-                    else z[zz[u]] = v;
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                    const double exact = (((double)c6[r] * 256.0 + (double)c5[r]) * 256.0 + (double)c4[r]) * 256.0 +
+                                         (double)c3[r];
+                    P[(32 * wave + row) * kPS + 32 * h + col] = ((float)exact * ds[row]) * sv;
                 }
             }
         }
-        __syncthreads();   // the stage is complete (the next tile's first barrier guards its reuse)
-        const int n = min(zcnt, cap);
-        for (int i = threadIdx.x; i < n; i += kWG) z[zbeg + i] = stage[i];
+        __syncthreads();
+        const int wi = (chunk * T + t) * kChunkWaves + wave;
+        const int eb = uni(wc_wave[wi]), ee = uni(wc_wave[wi + 1]);
+        if (eb >= ee) continue;
+        int run = uni(wc_wrun[wi]);      // index of the run open before the current batch, plus one
+        float carry = 0.f;
+        int kn = eb + lane < ee ? (int)wkey[eb + lane] : (int)life::kRunStart;
+        float pn = eb + lane < ee ? wphi[eb + lane] : 0.f;
+        for (int b = eb; b < ee; b += 64) {
+            const int key = kn;
+            const float ph = pn;
+            const int e2 = b + 64 + lane;
+            kn = e2 < ee ? (int)wkey[e2] : (int)life::kRunStart;
+            pn = e2 < ee ? wphi[e2] : 0.f;
+            const bool in = b + lane < ee;
+            const bool st = (key & life::kRunStart) != 0;
+            float v = in ? ph * P[((key >> 6) & 0x1ff) * kPS + (key & 63)] : 0.f;
+            if (lane == 0 && !st) v += carry;
+            // inclusive segmented scan (a run start stops the sums from the left)
+            int f = st ? 1 : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const float vu = __shfl_up(v, d, 64);
+                const int fu = __shfl_up(f, d, 64);
+                if (lane >= d && !f) {
+                    v += vu;
+                    f |= fu;
+                }
+            }
+            const uint64_t starts = __ballot(st);
+            const int next_key0 = __shfl(kn, 0, 64);   // the entry after this batch (a start past the range)
+            const bool nxt = lane < 63 ? ((starts >> (lane + 1)) & 1) != 0 : (next_key0 & life::kRunStart) != 0;
+            const int before = __popcll(starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+            if (in && nxt) zrun[run + before - 1] = v;
+            run += __popcll(starts & __ballot(in));
+            carry = __shfl(v, 63, 64);   // used only if the next batch does not start a run
+        }
     }
 }
 
@@ -1039,9 +1075,9 @@ int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // several streams at once.
 struct Workspace {
     float *w_rank = nullptr;      // [Nf] weights (or g~) in fascicle-rank order
-    h8 *dt_frag = nullptr;        // [n_tiles][dt_ab][dt_ks][2][64] split D^T operands of WC pass 1
+    i32x4 *dt_frag = nullptr;     // [n_tiles][dt_ab][dt_ks][kDigits][64] digits of D^T, the A operands of WC pass 1
     float *dt_scale = nullptr;    // [n_tiles][dt_ab][32]
-    float *z = nullptr;           // [max(nnz, n_pad)] WC pass-1 values
+    float *z = nullptr;           // WC pass-1 values: one per run (chunked plans) or per nonzero
     float *r = nullptr, *vp = nullptr;                                // [Nt*Nv] SBB residual, M q
     float *g = nullptr, *gt = nullptr, *vpp = nullptr, *q = nullptr;  // [Nf] SBB vectors
     double *part = nullptr;       // 5 regions of part_stride partial sums
@@ -1071,15 +1107,24 @@ struct life_plan_s {
     std::vector<int64_t> chunk_work;   // host: padded entries per chunk (for re-scheduling)
     int32_t *wave_work = nullptr; // [n_chunks * n_tiles * kChunkWaves * kWorkInts]
     int16_t *atom_c = nullptr;    // [n_pad]
-    int32_t *fas_c = nullptr;     // [n_pad]
+    int32_t *fas_c = nullptr;     // [n_pad] fascicle rank
+    uint16_t *loc_c = nullptr;    // [n_pad] place of the fascicle in its chunk's list
     float *phi_c = nullptr;       // [n_pad]
-    int32_t *z_pos = nullptr;     // [n_pad] z position of each padded entry
-    int32_t *wc_perm_z = nullptr; // [nnz] z position of each WC slot
-    int32_t *tile_z = nullptr;    // [n_chunks * n_tiles * 2] first z position and count per (chunk, tile)
+    int32_t *cfas_ptr = nullptr;  // [n_chunks + 1] chunk fascicle lists (see life::ChunkLayout)
+    int32_t *cfas = nullptr;
+    int max_fas = 0;              // longest chunk fascicle list
+    size_t dsc_lds = 0;
+    // WC pass 1 buckets (see life::ChunkLayout) and pass 2 run lists
+    uint16_t *wkey = nullptr;     // [nnz]
+    float *wphi = nullptr;        // [nnz]
+    int32_t *wc_wave = nullptr;   // [n_chunks * n_tiles * kChunkWaves + 1]
+    int32_t *wc_wrun = nullptr;   // [n_chunks * n_tiles * kChunkWaves]
+    int64_t n_runs = 0;
+    int32_t *rr_ptr = nullptr;    // [Nf + 1]
+    int32_t *rr = nullptr;        // [n_runs]
     // WC pass 1 on the matrix cores: split D^T operands (k_split_dt) and the LDS size
-    int dt_ab = 0, dt_ks = 0;     // atom blocks of 32 per tile, k-steps of 16 theta
-    int wcz_cap = 0;              // floats of LDS that stage a tile's z values (0: none)
-    size_t wcz_lds = 0;
+    int dt_ab = 0, dt_ks = 0;     // atom blocks of 32 per tile, k-steps of 32 theta
+    size_t wcr_lds = 0;
     // fascicles are processed in rank order (fas_v holds ranks)
     int32_t *fas_rank = nullptr;  // [Nf] rank of each fascicle
     int32_t *fas_ext = nullptr;   // [Nf] fascicle of each rank
@@ -1134,7 +1179,8 @@ hipError_t dalloc(T **p, int64_t n)
 void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c,
-                    p->fas_c, p->phi_c, p->z_pos, p->wc_perm_z, p->tile_z, p->fas_rank, p->fas_ext, p->fas_ptr,
+                    p->fas_c, p->loc_c, p->phi_c, p->cfas_ptr, p->cfas, p->wkey, p->wphi, p->wc_wave, p->wc_wrun,
+                    p->rr_ptr, p->rr, p->fas_rank, p->fas_ext, p->fas_ptr,
                     p->wc_perm, p->ws_base, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -1162,10 +1208,10 @@ size_t workspace_layout(const life_plan_s *p, unsigned need, char *base, Workspa
     if (need & (kWsDsc | kWsSbb | kWsDd)) take(&w.w_rank, nf, sizeof(float));
     if (need & (kWsWc | kWsSbb)) {
         if (p->n_chunks > 0) {
-            take(&w.dt_frag, (int64_t)p->tile.n_tiles * p->dt_ab * p->dt_ks * 2 * 64, sizeof(h8));
+            take(&w.dt_frag, (int64_t)p->tile.n_tiles * p->dt_ab * p->dt_ks * kDigits * 64, sizeof(i32x4));
             take(&w.dt_scale, (int64_t)p->tile.n_tiles * p->dt_ab * 32, sizeof(float));
         }
-        take(&w.z, std::max<int64_t>(d.nnz, p->n_pad), sizeof(float));
+        take(&w.z, p->n_chunks > 0 ? p->n_runs : d.nnz, sizeof(float));
     }
     if (need & kWsSbb) {
         take(&w.r, nsig, sizeof(float));
@@ -1195,13 +1241,14 @@ template <class F>
 life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p->profile) {
+    const bool prof = p->profile;
+    if (prof) {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
         if (hipEventRecord(e0, s) != hipSuccess) return LIFE_EDEVICE;
     }
     f();
     const hipError_t err = hipGetLastError();
-    if (p->profile) {
+    if (prof) {
         if (hipEventRecord(e1, s) != hipSuccess) return LIFE_EDEVICE;
         p->events.push_back({kind, {e0, e1}});
     }
@@ -1266,7 +1313,7 @@ hipError_t allow_lds()
 {
     const int bytes = life::kLdsBudget;
     const void *fns[] = {(const void *)k_dsc_chunk<1>, (const void *)k_dsc_chunk<2>, (const void *)k_dsc_chunk<3>,
-                         (const void *)k_dsc_chunk<4>, (const void *)k_wcz_mfma, (const void *)k_dd_chunk<1>,
+                         (const void *)k_dsc_chunk<4>, (const void *)k_wcr_mfma, (const void *)k_dd_chunk<1>,
                          (const void *)k_dd_chunk<2>, (const void *)k_dd_chunk<3>, (const void *)k_dd_chunk<5>,
                          (const void *)k_dd_chunk<9>, (const void *)k_dd_chunk<12>};
     for (const void *f : fns) {
@@ -1288,13 +1335,13 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
     if (nv == 0) return LIFE_OK;
     if (chunked(p)) {
         const int nc = p->tile.row_floats / 32;
-        const size_t lds = tile_lds_bytes(p);
         return launch(p, LIFE_K_DSC, s, [&] {
-            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->chunk_grid, kWG, lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work,
-                                                                           p->atom_c,
-                                                                           p->fas_c, p->phi_c, w, D, bsub, y, part,
-                                                                           nth, p->dims.n_atoms, p->tile.n_tiles,
-                                                                           p->tile.tile_atoms, vec_tile(p, D)))
+            LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->chunk_grid, kWG, p->dsc_lds, s>>>(p->chunk_map, p->chunk_vox,
+                                                                                  p->wave_work, p->atom_c, p->loc_c,
+                                                                                  p->phi_c, p->cfas_ptr, p->cfas, w, D,
+                                                                                  bsub, y, part, nth,
+                                                                                  p->dims.n_atoms, p->tile.n_tiles,
+                                                                                  p->tile.tile_atoms, vec_tile(p, D)))
         });
     }
     const int grid = cdiv(nv, kSegPerBlock);
@@ -1319,10 +1366,9 @@ life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, cons
                     k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, ws.dt_frag, ws.dt_scale,
                                                                                          nth, p->dims.n_atoms, T, TA,
                                                                                          AB, KS, gate);
-                k_wcz_mfma<<<p->chunk_grid, kWG, p->wcz_lds, s>>>(p->chunk_map, p->chunk_vox, p->wave_work, p->atom_c,
-                                                                  p->phi_c, p->z_pos, p->tile_z, ws.dt_frag,
-                                                                  ws.dt_scale, y, ws.z, nth, T, TA, AB, KS,
-                                                                  p->wcz_cap, gate);
+                k_wcr_mfma<<<p->chunk_grid, kWG, p->wcr_lds, s>>>(p->chunk_map, p->chunk_vox, p->wkey, p->wphi,
+                                                                  p->wc_wave, p->wc_wrun, ws.dt_frag, ws.dt_scale, y,
+                                                                  ws.z, nth, T, AB, KS, gate);
             });
         } else {
             const int grid = cdiv(nv, kSegPerBlock);
@@ -1336,7 +1382,8 @@ life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, cons
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
         st = launch(p, gate.st ? LIFE_K_WC_SUM_2ND : LIFE_K_WC_SUM, s, [&] {
-            k_wc_sum<<<grid, kBlock, 0, s>>>(p->fas_ptr, chunked(p) ? p->wc_perm_z : p->wc_perm, ws.z, gmap, g,
+            k_wc_sum<<<grid, kBlock, 0, s>>>(chunked(p) ? p->rr_ptr : p->fas_ptr, chunked(p) ? p->rr : p->wc_perm,
+                                             ws.z, gmap, g,
                                              part, nf, gate);
         });
     }
@@ -1411,15 +1458,14 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         vox_off = one_v;
         fas_off = one_f;
     }
-    std::vector<int32_t> perm, vptr, wperm, fptr, tptr, cvox, rank, ext, wwork, zpos, wperm_z, tilez, ppos, pvox, vdsc;
+    std::vector<int32_t> perm, vptr, wperm, fptr, rank, ext, ppos, pvox, vdsc;
     std::vector<int32_t> aptr, avox, afas, cmap;
-    std::vector<int64_t> chunk_work;
     std::vector<float> aphi;
-    std::vector<int16_t> atom_v, atom_c;
-    std::vector<int32_t> fas_v, fas_c;
-    std::vector<float> phi_v, phi_c;
+    std::vector<int16_t> atom_v;
+    std::vector<int32_t> fas_v;
+    std::vector<float> phi_v;
     std::vector<int32_t> ichunk((size_t)n_inst + 1, 0);
-    int64_t n_pad = 0;
+    life::ChunkLayout L;
     const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
     if (batched) {
         if (tg.row_floats == 0) return LIFE_EINVAL;   // batched plans need N_theta <= 128
@@ -1428,7 +1474,7 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     }
     const int32_t n_pos = life::padded_positions(&d, n_inst, vox_off);
     if (n_pos < 0) return LIFE_ERANGE;
-    const int n_chunks = tg.row_floats > 0 ? cdiv(n_pos, kChunkVoxels) : 0;
+    int n_chunks = 0;
     try {
         perm.resize((size_t)d.nnz);
         wperm.resize((size_t)d.nnz);
@@ -1443,14 +1489,8 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         if (batched) {
             // each instance's fascicles take one contiguous block of ranks
             fas_inst.resize((size_t)d.n_fascicles);
-            int32_t base = 0;
-            for (int k = 0; k < n_inst; ++k) {
-                base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
-                ichunk[(size_t)k + 1] = base / kChunkVoxels;
+            for (int k = 0; k < n_inst; ++k)
                 for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) fas_inst[(size_t)f] = k;
-            }
-        } else {
-            ichunk[1] = n_chunks;
         }
         st = life::plan_host(&d, atom, voxel, fascicle, (voxel_xyz || batched) ? ppos.data() : nullptr, n_pos,
                              batched ? fas_inst.data() : nullptr, perm.data(), vptr.data(), rank.data(),
@@ -1467,6 +1507,29 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             fas_v[(size_t)p] = rank[(size_t)fascicle[c]];
             phi_v[(size_t)p] = phi[c];
             vdsc[(size_t)p] = voxel[c];
+        }
+        if (tg.row_floats > 0) {
+            st = life::chunk_layout(&d, tg, vptr.data(), atom_v.data(), fas_v.data(), phi_v.data(), vdsc.data(),
+                                    wperm.data(), ppos.data(), pvox.data(), n_pos, &L);
+            if (st != LIFE_OK) return st;
+            if (L.fas_overflow) {
+                // a voxel crosses more fascicles than a chunk can hold: generic kernels
+                if (batched) return LIFE_EINVAL;
+                L = life::ChunkLayout();
+            }
+            n_chunks = L.n_chunks;
+        }
+        if (batched) {
+            // first chunk of each instance: instance blocks are whole groups of positions
+            int32_t base = 0;
+            size_t c = 0;
+            for (int k = 0; k < n_inst; ++k) {
+                base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
+                while (c < L.bounds.size() && L.bounds[c] < base) ++c;
+                ichunk[(size_t)k + 1] = static_cast<int32_t>(c);
+            }
+        } else {
+            ichunk[1] = n_chunks;
         }
         if (n_chunks == 0 && d.nnz > 0) {
             // atom-major copy of the nonzeros for the generic dictionary gradient
@@ -1485,28 +1548,14 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             }
         }
         if (n_chunks > 0) {
-            tptr.resize((size_t)d.n_voxels * (tg.n_tiles + 1));
-            cvox.resize((size_t)n_chunks * kChunkVoxels);
-            life::chunk_plan(&d, tg, vptr.data(), atom_v.data(), pvox.data(), n_pos, tptr.data(), cvox.data());
-            n_pad = life::chunked_arrays(&d, tg, n_chunks, tptr.data(), cvox.data(), ppos.data(), atom_v.data(),
-                                         fas_v.data(), phi_v.data(), vdsc.data(), wperm.data(), wwork, atom_c,
-                                         fas_c, phi_c, zpos, wperm_z, tilez);
-            if (n_pad < 0) return LIFE_ERANGE;
-            std::vector<int64_t> work((size_t)n_chunks);
-            const size_t per_chunk = (size_t)tg.n_tiles * kChunkWaves * life::kWorkInts;
-            for (int c = 0; c < n_chunks; ++c) {
-                const int64_t end = c + 1 < n_chunks ? wwork[(size_t)(c + 1) * per_chunk] : n_pad;
-                work[(size_t)c] = end - wwork[(size_t)c * per_chunk];
-            }
             // one grid length for every schedule policy (the longest map, the others
             // padded with -1), so that re-scheduling keeps the map's address and the
             // grid of launches already captured in a graph
             size_t grid = 0;
             for (int pol : {life::kScheduleIndex, life::kScheduleXcdCount, life::kScheduleXcdWork})
-                grid = std::max(grid, life::chunk_schedule(work, (life::SchedulePolicy)pol).size());
-            cmap = life::chunk_schedule(work, life::kScheduleDefault);
+                grid = std::max(grid, life::chunk_schedule(L.work, (life::SchedulePolicy)pol).size());
+            cmap = life::chunk_schedule(L.work, life::kScheduleDefault);
             cmap.resize(grid, -1);
-            chunk_work.swap(work);
         }
     } catch (const std::bad_alloc &) {
         return LIFE_ENOMEM;
@@ -1522,9 +1571,11 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     p->slots = slots_for(d.n_theta);
     p->tile = tg;
     p->n_chunks = n_chunks;
-    p->n_pad = n_pad;
+    p->n_pad = L.n_pad;
     p->chunk_grid = (int)cmap.size();
-    p->chunk_work.swap(chunk_work);
+    p->chunk_work = L.work;
+    p->max_fas = L.max_fas;
+    p->n_runs = L.n_runs;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
     p->part_stride = nb;
@@ -1548,18 +1599,19 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         p->dd_nbw = dd_nbw_variant((nb_blocks + kChunkWaves - 1) / kChunkWaves);
         p->dd_floats = (int64_t)DT * p->dd_groups * p->dd_tap * nt16;
         p->dt_ab = (tg.tile_atoms + 31) / 32;
-        p->dt_ks = (d.n_theta + 15) / 16;
-        p->wcz_lds = (size_t)p->dt_ab * 32 * kPS * sizeof(float) +
-                     (size_t)2 * kChunkVoxels * (16 * p->dt_ks + 8) * sizeof(_Float16) + kChunkVoxels * sizeof(float);
+        p->dt_ks = (d.n_theta + 31) / 32;
+        p->wcr_lds = (size_t)p->dt_ab * 32 * kPS * sizeof(float) +
+                     (size_t)kDigits * kChunkVoxels * (32 * p->dt_ks + kQ8Pad) +
+                     kChunkVoxels * sizeof(float);
+        // DSC: the dictionary tile, then one weight per fascicle of the chunk
+        p->dsc_lds = tile_lds_bytes(p) + (size_t)p->max_fas * sizeof(float);
         if (p->dd_nbw < 0 ||
             (int64_t)(p->dd_tap + (d.n_theta + 15) / 16 * 16) * kPsiStride * 4 > life::kLdsBudget ||
-            p->dt_ab > kChunkWaves || p->dt_ks > 8 || p->wcz_lds > (size_t)life::kLdsBudget) {
+            p->dt_ab > kChunkWaves || p->dt_ks > 4 || p->wcr_lds > (size_t)life::kLdsBudget ||
+            p->dsc_lds > (size_t)life::kLdsBudget) {
             delete p;
             return LIFE_EINVAL;   // cannot happen: tiles hold at most kMaxTileAtoms atoms, N_theta <= 128
         }
-        // the rest of the LDS budget stages z (whole 16-byte units)
-        p->wcz_cap = (int)(((size_t)life::kLdsBudget - p->wcz_lds) / 16 * 4);
-        p->wcz_lds += (size_t)p->wcz_cap * sizeof(float);
     }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -1567,15 +1619,21 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     chk(dalloc(&p->atom_v, d.nnz));
     chk(dalloc(&p->fas_v, d.nnz));
     chk(dalloc(&p->phi_v, d.nnz));
-    chk(dalloc(&p->chunk_vox, (int64_t)cvox.size()));
+    chk(dalloc(&p->chunk_vox, (int64_t)L.chunk_vox.size()));
     chk(dalloc(&p->chunk_map, (int64_t)cmap.size()));
-    chk(dalloc(&p->wave_work, (int64_t)wwork.size()));
-    chk(dalloc(&p->atom_c, n_pad));
-    chk(dalloc(&p->fas_c, n_pad));
-    chk(dalloc(&p->phi_c, n_pad));
-    chk(dalloc(&p->z_pos, (int64_t)zpos.size()));
-    chk(dalloc(&p->wc_perm_z, (int64_t)wperm_z.size()));
-    chk(dalloc(&p->tile_z, (int64_t)tilez.size()));
+    chk(dalloc(&p->wave_work, (int64_t)L.wave_work.size()));
+    chk(dalloc(&p->atom_c, (int64_t)L.atom_c.size()));
+    chk(dalloc(&p->fas_c, (int64_t)L.fas_c.size()));
+    chk(dalloc(&p->loc_c, (int64_t)L.loc_c.size()));
+    chk(dalloc(&p->phi_c, (int64_t)L.phi_c.size()));
+    chk(dalloc(&p->cfas_ptr, (int64_t)L.cfas_ptr.size()));
+    chk(dalloc(&p->cfas, (int64_t)L.cfas.size()));
+    chk(dalloc(&p->wkey, (int64_t)L.wkey.size()));
+    chk(dalloc(&p->wphi, (int64_t)L.wphi.size()));
+    chk(dalloc(&p->wc_wave, (int64_t)L.wc_wave.size()));
+    chk(dalloc(&p->wc_wrun, (int64_t)L.wc_wrun.size()));
+    chk(dalloc(&p->rr_ptr, (int64_t)L.rr_ptr.size()));
+    chk(dalloc(&p->rr, (int64_t)L.rr.size()));
     chk(dalloc(&p->fas_rank, d.n_fascicles));
     chk(dalloc(&p->fas_ext, d.n_fascicles));
     chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
@@ -1605,15 +1663,22 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     up(p->atom_v, atom_v.data(), sizeof(int16_t) * atom_v.size());
     up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
     up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
-    up(p->chunk_vox, cvox.data(), sizeof(int32_t) * cvox.size());
-    up(p->chunk_map, cmap.data(), sizeof(int32_t) * cmap.size());
-    up(p->wave_work, wwork.data(), sizeof(int32_t) * wwork.size());
-    up(p->atom_c, atom_c.data(), sizeof(int16_t) * atom_c.size());
-    up(p->fas_c, fas_c.data(), sizeof(int32_t) * fas_c.size());
-    up(p->phi_c, phi_c.data(), sizeof(float) * phi_c.size());
-    up(p->z_pos, zpos.data(), sizeof(int32_t) * zpos.size());
-    up(p->wc_perm_z, wperm_z.data(), sizeof(int32_t) * wperm_z.size());
-    up(p->tile_z, tilez.data(), sizeof(int32_t) * tilez.size());
+    auto upv = [&](void *dst, const auto &v) { up(dst, v.data(), sizeof(v[0]) * v.size()); };
+    upv(p->chunk_vox, L.chunk_vox);
+    upv(p->chunk_map, cmap);
+    upv(p->wave_work, L.wave_work);
+    upv(p->atom_c, L.atom_c);
+    upv(p->fas_c, L.fas_c);
+    upv(p->loc_c, L.loc_c);
+    upv(p->phi_c, L.phi_c);
+    upv(p->cfas_ptr, L.cfas_ptr);
+    upv(p->cfas, L.cfas);
+    upv(p->wkey, L.wkey);
+    upv(p->wphi, L.wphi);
+    upv(p->wc_wave, L.wc_wave);
+    upv(p->wc_wrun, L.wc_wrun);
+    upv(p->rr_ptr, L.rr_ptr);
+    upv(p->rr, L.rr);
     up(p->fas_rank, rank.data(), sizeof(int32_t) * rank.size());
     up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
     up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());

@@ -72,13 +72,18 @@ struct TileGeom {
 
 TileGeom tile_geometry(int n_theta, int n_atoms);
 
-// tile_ptr[v*(n_tiles+1) + t]: first DSC position of voxel v whose atom is >= t*tile_atoms
-// (the segment's atoms are ascending); tile_ptr[v*(n_tiles+1) + n_tiles] = end of segment.
-// chunk_vox[c*kChunkVoxels + wave*kWaveVoxels + j]: voxel owned by slot j of a wave in chunk c
-// (-1 = empty), balanced inside each chunk by longest-processing-time assignment;
-// chunk c holds processing positions [64c, 64c + 64) of n_pos.
-void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                const int32_t *proc_vox, int32_t n_pos, int32_t *tile_ptr, int32_t *chunk_vox);
+// Chunks.  Processing positions are cut into groups of kChunkVoxels consecutive
+// positions (instance blocks of batched plans are whole groups, so no group spans
+// two instances).  A group becomes one chunk, or, when its nonzeros cross more
+// than kChunkFasCap distinct fascicles, is halved (recursively) into chunks that
+// cross at most that many: the chunked kernels keep one value per distinct
+// fascicle of their chunk in LDS (the DSC weights, the WC partial sums).  A
+// single voxel that crosses more fascicles makes the plan fall back to the
+// generic kernels.  A chunk is one workgroup of kChunkWaves waves; each wave owns
+// up to kWaveVoxels voxel slots, balanced inside the chunk by longest-processing-
+// time assignment (ties keep processing order).
+constexpr int kChunkFasCap = 16384;
+constexpr uint16_t kRunStart = 0x8000;
 
 // Chunked layout: for every (chunk c, tile t, wave w) one contiguous range of the
 // padded arrays holds the tile-t sub-ranges of the wave's voxel slots j = 0..3,
@@ -91,8 +96,49 @@ void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, 
 //   (slot j owns steps [E_j, E_{j+1}), E_0 = 0; kStepEntries entries per step).
 constexpr int kStepEntries = 4;
 constexpr int kWorkInts = 5;
-int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
-                     int n_chunks, int32_t *wave_work, int32_t *chunk_pos);
+
+struct ChunkLayout {
+    int n_chunks = 0;
+    int64_t n_pad = 0;                  // padded entries
+    bool fas_overflow = false;          // a single voxel crosses more than kChunkFasCap fascicles
+    int max_fas = 0;                    // largest number of distinct fascicles of a chunk
+    std::vector<int32_t> bounds;        // [n_chunks + 1] processing-position range of each chunk
+    std::vector<int32_t> chunk_vox;     // [n_chunks * kChunkVoxels] voxel of each slot, -1 = empty
+    std::vector<int32_t> wave_work;     // [n_chunks * T * kChunkWaves * kWorkInts]
+    std::vector<int64_t> work;          // [n_chunks] padded entries of each chunk
+    // padded DSC-order copies: atom, fascicle rank, local fascicle index, value
+    std::vector<int16_t> atom_c;
+    std::vector<int32_t> fas_c;
+    std::vector<uint16_t> loc_c;
+    std::vector<float> phi_c;
+    // chunk fascicle lists: chunk c crosses the ranks cfas[cfas_ptr[c] .. cfas_ptr[c+1])
+    // (ascending); an entry's local index is its rank's place in that list
+    std::vector<int32_t> cfas_ptr, cfas;
+    // WC pass 1: the nonzeros of each (chunk, tile) bucket ct = c T + t, in WC order
+    // (rank, voxel position, atom, ...), at [wc_ent[ct], wc_ent[ct + 1]):
+    //   wkey = kRunStart (first entry of a run of one fascicle) | (atom - t TA) << 6
+    //          | voxel slot;   wphi = value.
+    // Runs are numbered in entry order.  Wave w of the bucket's workgroup takes the
+    // entries [wc_wave[ct W + w], wc_wave[ct W + w + 1]) (W = kChunkWaves; the cuts
+    // fall on run starts, so no run is split), whose first run is wc_wrun[ct W + w].
+    std::vector<int32_t> wc_ent;
+    std::vector<uint16_t> wkey;
+    std::vector<float> wphi;
+    std::vector<int32_t> wc_wave, wc_wrun;
+    int64_t n_runs = 0;
+    // WC pass 2: the fascicle of rank r sums the run values of runs
+    // rr[rr_ptr[r] .. rr_ptr[r+1]) (ascending)
+    std::vector<int32_t> rr_ptr, rr;
+};
+
+// The chunked layout from the canonical DSC-order arrays (atom_v, fas_v = ranks,
+// phi_v, voxel of each DSC position), the WC permutation (wc_perm), the segment
+// offsets vox_ptr and the processing order (proc_pos / proc_vox over n_pos
+// positions).  Returns LIFE_ERANGE if a padded length exceeds the 32-bit limit.
+life_status chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_v,
+                         const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
+                         const int32_t *wc_perm, const int32_t *proc_pos, const int32_t *proc_vox, int32_t n_pos,
+                         ChunkLayout *out);
 
 // Workgroup-to-chunk map of the chunked kernels (chunk or -1 per workgroup).
 // Consecutive workgroups are dispatched to the 8 XCDs in turn, so workgroup i
@@ -105,21 +151,5 @@ enum SchedulePolicy { kScheduleIndex = 0, kScheduleXcdCount = 1, kScheduleXcdWor
 constexpr SchedulePolicy kScheduleDefault = kScheduleIndex;
 constexpr int kXcds = 8;
 std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePolicy policy);
-
-// The padded arrays of the chunked layout from the canonical DSC-order arrays:
-// pad entries get value 0, the atom of the entry before them and fascicle rank 0.  The WC
-// pass-1 output z uses its own order inside each chunk's range: the chunk's
-// entries tile by tile, in WC order inside a tile (so one fascicle's entries of
-// one tile in one chunk are adjacent, and the writes of one tile's pass stay in
-// one sub-range), then its pad entries.  z_pos[q] = z position of padded entry q;
-// wc_perm_z[j] = z position of WC slot j; tile_z[2 (c T + t)] and [.. + 1] = first
-// z position and number of the (real) entries of chunk c in tile t.  Returns the
-// padded length, or -1 if it exceeds the 32-bit position limit.
-int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
-                       const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
-                       const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
-                       const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
-                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
-                       std::vector<int32_t> &wc_perm_z, std::vector<int32_t> &tile_z);
 
 }  // namespace life

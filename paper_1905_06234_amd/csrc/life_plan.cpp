@@ -255,64 +255,116 @@ TileGeom tile_geometry(int n_theta, int n_atoms)
     return g;
 }
 
-void chunk_plan(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_sorted,
-                const int32_t *proc_vox, int32_t n_pos, int32_t *tile_ptr, int32_t *chunk_vox)
+namespace {
+
+// Distinct fascicle ranks of the nonzeros of processing positions [pb, pe);
+// stamp[rank] == tag marks a rank already counted (tags never repeat).
+int distinct_fascicles(const int32_t *vox_ptr, const int32_t *fas_v, const int32_t *proc_vox, int32_t pb, int32_t pe,
+                       std::vector<int64_t> &stamp, int64_t tag)
 {
-    const int nv = d->n_voxels, T = tg.n_tiles;
+    int n = 0;
+    for (int32_t k = pb; k < pe; ++k) {
+        const int32_t v = proc_vox ? proc_vox[k] : k;
+        if (v < 0) continue;
+        for (int32_t q = vox_ptr[v]; q < vox_ptr[v + 1]; ++q)
+            if (stamp[(size_t)fas_v[q]] != tag) {
+                stamp[(size_t)fas_v[q]] = tag;
+                ++n;
+            }
+    }
+    return n;
+}
+
+}  // namespace
+
+life_status chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_v,
+                         const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
+                         const int32_t *wc_perm, const int32_t *proc_pos, const int32_t *proc_vox, int32_t n_pos,
+                         ChunkLayout *out)
+{
+    ChunkLayout &L = *out;
+    const int nv = d->n_voxels, nf = d->n_fascicles, T = tg.n_tiles, TA = tg.tile_atoms;
+    const int64_t nnz = d->nnz;
+    // per voxel: first DSC position of each tile (atoms ascend inside a segment)
+    std::vector<int32_t> tile_ptr((size_t)nv * (T + 1));
     for (int v = 0; v < nv; ++v) {
         int p = vox_ptr[v];
         const int end = vox_ptr[v + 1];
         for (int t = 0; t < T; ++t) {
-            const int lo = t * tg.tile_atoms;
-            while (p < end && atom_sorted[p] < lo) ++p;
-            tile_ptr[(int64_t)v * (T + 1) + t] = p;
+            while (p < end && atom_v[p] < t * TA) ++p;
+            tile_ptr[(size_t)v * (T + 1) + t] = p;
         }
-        tile_ptr[(int64_t)v * (T + 1) + T] = end;
+        tile_ptr[(size_t)v * (T + 1) + T] = end;
     }
-    const int nchunks = (n_pos + kChunkVoxels - 1) / kChunkVoxels;
+    // chunk bounds: groups of kChunkVoxels positions, halved while they cross too
+    // many distinct fascicles
+    std::vector<int64_t> stamp((size_t)nf, -1);
+    int64_t tag = 0;
+    L.bounds.assign(1, 0);
+    L.fas_overflow = false;
+    std::vector<std::pair<int32_t, int32_t>> todo;
+    for (int32_t g0 = 0; g0 < n_pos; g0 += kChunkVoxels) {
+        todo.assign(1, {g0, std::min(n_pos, g0 + kChunkVoxels)});
+        while (!todo.empty()) {
+            const auto r = todo.back();
+            todo.pop_back();
+            const int n = distinct_fascicles(vox_ptr, fas_v, proc_vox, r.first, r.second, stamp, tag++);
+            if (n > kChunkFasCap && r.second - r.first > 1) {
+                const int32_t mid = r.first + (r.second - r.first) / 2;
+                todo.push_back({mid, r.second});   // LIFO: the lower half is cut first
+                todo.push_back({r.first, mid});
+                continue;
+            }
+            if (n > kChunkFasCap) L.fas_overflow = true;
+            L.bounds.push_back(r.second);
+        }
+    }
+    const int nc = (int)L.bounds.size() - 1;
+    L.n_chunks = nc;
+    // voxel slots of each chunk (longest first; ties keep processing order)
+    L.chunk_vox.assign((size_t)nc * kChunkVoxels, -1);
+    std::vector<int32_t> vox_chunk((size_t)nv, -1), vox_slot((size_t)nv, -1);
     std::vector<int> ids;
-    for (int c = 0; c < nchunks; ++c) {
-        const int k0 = c * kChunkVoxels, k1 = std::min(n_pos, k0 + kChunkVoxels);
+    for (int c = 0; c < nc; ++c) {
         ids.clear();
-        for (int k = k0; k < k1; ++k) {
+        for (int32_t k = L.bounds[c]; k < L.bounds[c + 1]; ++k) {
             const int v = proc_vox ? proc_vox[k] : k;
             if (v >= 0) ids.push_back(v);
         }
-        // longest first; ties keep processing order so the plan is unique
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
             return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
         });
         int64_t load[kChunkWaves] = {0};
         int fill[kChunkWaves] = {0};
-        int32_t *slots = chunk_vox + (int64_t)c * kChunkVoxels;
-        for (int i = 0; i < kChunkVoxels; ++i) slots[i] = -1;
+        int32_t *slots = L.chunk_vox.data() + (size_t)c * kChunkVoxels;
         for (int v : ids) {
             int best = -1;
             for (int wv = 0; wv < kChunkWaves; ++wv)
                 if (fill[wv] < kWaveVoxels && (best < 0 || load[wv] < load[best])) best = wv;
-            slots[best * kWaveVoxels + fill[best]++] = v;
+            const int slot = best * kWaveVoxels + fill[best]++;
+            slots[slot] = v;
+            vox_chunk[(size_t)v] = c;
+            vox_slot[(size_t)v] = slot;
             load[best] += vox_ptr[v + 1] - vox_ptr[v];
         }
     }
-}
-
-int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile_ptr, const int32_t *chunk_vox,
-                     int n_chunks, int32_t *wave_work, int32_t *chunk_pos)
-{
-    (void)d;
-    const int T = tg.n_tiles;
+    // padded positions of the DSC entries and the wave ranges
+    L.wave_work.assign((size_t)nc * T * kChunkWaves * kWorkInts, 0);
+    std::vector<int32_t> cpos((size_t)nnz);
+    L.work.assign((size_t)nc, 0);
     int64_t q = 0;
-    for (int c = 0; c < n_chunks; ++c)
+    for (int c = 0; c < nc; ++c) {
+        const int64_t q_chunk = q;
         for (int t = 0; t < T; ++t)
             for (int w = 0; w < kChunkWaves; ++w) {
-                int32_t *ww = wave_work + ((int64_t)(c * T + t) * kChunkWaves + w) * kWorkInts;
+                int32_t *ww = &L.wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
                 ww[0] = static_cast<int32_t>(std::min<int64_t>(q, kMaxNnz));
                 int steps = 0;
                 for (int j = 0; j < kWaveVoxels; ++j) {
-                    const int v = chunk_vox[(int64_t)c * kChunkVoxels + w * kWaveVoxels + j];
+                    const int v = L.chunk_vox[(size_t)c * kChunkVoxels + w * kWaveVoxels + j];
                     if (v >= 0) {
-                        const int32_t p0 = tile_ptr[(int64_t)v * (T + 1) + t], p1 = tile_ptr[(int64_t)v * (T + 1) + t + 1];
-                        for (int32_t p = p0; p < p1; ++p) chunk_pos[p] = static_cast<int32_t>(q + (p - p0));
+                        const int32_t p0 = tile_ptr[(size_t)v * (T + 1) + t], p1 = tile_ptr[(size_t)v * (T + 1) + t + 1];
+                        for (int32_t p = p0; p < p1; ++p) cpos[(size_t)p] = static_cast<int32_t>(q + (p - p0));
                         const int ns = (p1 - p0 + kStepEntries - 1) / kStepEntries;
                         q += kStepEntries * (int64_t)ns;
                         steps += ns;
@@ -320,9 +372,121 @@ int64_t chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *tile
                     ww[1 + j] = steps;
                 }
             }
-    return q;
+        L.work[(size_t)c] = q - q_chunk;
+    }
+    if (q > kMaxNnz) return LIFE_ERANGE;
+    L.n_pad = q;
+    // chunk fascicle lists and local indices
+    L.cfas_ptr.assign((size_t)nc + 1, 0);
+    L.cfas.clear();
+    std::vector<int32_t> loc_of((size_t)nf, -1);
+    std::vector<int32_t> list;
+    L.max_fas = 0;
+    for (int c = 0; c < nc; ++c) {
+        list.clear();
+        ++tag;
+        for (int32_t k = L.bounds[c]; k < L.bounds[c + 1]; ++k) {
+            const int v = proc_vox ? proc_vox[k] : k;
+            if (v < 0) continue;
+            for (int32_t p = vox_ptr[v]; p < vox_ptr[v + 1]; ++p)
+                if (stamp[(size_t)fas_v[p]] != tag) {
+                    stamp[(size_t)fas_v[p]] = tag;
+                    list.push_back(fas_v[p]);
+                }
+        }
+        std::sort(list.begin(), list.end());
+        L.cfas.insert(L.cfas.end(), list.begin(), list.end());
+        L.cfas_ptr[(size_t)c + 1] = static_cast<int32_t>(L.cfas.size());
+        L.max_fas = std::max(L.max_fas, (int)list.size());
+    }
+    if ((int64_t)L.cfas.size() > kMaxNnz) return LIFE_ERANGE;
+    // padded copies (pads: value 0, the atom before them, rank 0, local index 0)
+    L.atom_c.assign((size_t)L.n_pad, 0);
+    L.fas_c.assign((size_t)L.n_pad, 0);
+    L.loc_c.assign((size_t)L.n_pad, 0);
+    L.phi_c.assign((size_t)L.n_pad, 0.f);
+    for (int c = 0; c < nc; ++c) {
+        for (int32_t i = L.cfas_ptr[c]; i < L.cfas_ptr[c + 1]; ++i) loc_of[(size_t)L.cfas[i]] = i - L.cfas_ptr[c];
+        for (int32_t k = L.bounds[c]; k < L.bounds[c + 1]; ++k) {
+            const int v = proc_vox ? proc_vox[k] : k;
+            if (v < 0) continue;
+            for (int32_t p = vox_ptr[v]; p < vox_ptr[v + 1]; ++p) {
+                const size_t e = (size_t)cpos[(size_t)p];
+                L.atom_c[e] = atom_v[p];
+                L.fas_c[e] = fas_v[p];
+                L.loc_c[e] = static_cast<uint16_t>(loc_of[(size_t)fas_v[p]]);
+                L.phi_c[e] = phi_v[p];
+            }
+        }
+    }
+    for (int c = 0; c < nc; ++c)
+        for (int t = 0; t < T; ++t)
+            for (int w = 0; w < kChunkWaves; ++w) {
+                const int32_t *ww = &L.wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
+                for (int j = 0; j < kWaveVoxels; ++j) {
+                    const int v = L.chunk_vox[(size_t)c * kChunkVoxels + w * kWaveVoxels + j];
+                    if (v < 0) continue;
+                    const int64_t beg = ww[0] + (int64_t)kStepEntries * (j ? ww[j] : 0);
+                    const int64_t end = ww[0] + (int64_t)kStepEntries * ww[j + 1];
+                    const int64_t n_real = tile_ptr[(size_t)v * (T + 1) + t + 1] - tile_ptr[(size_t)v * (T + 1) + t];
+                    for (int64_t e = beg + n_real; e < end; ++e) L.atom_c[(size_t)e] = L.atom_c[(size_t)e - 1];
+                }
+            }
+    // WC pass 1: the WC order bucketed (stably) by (chunk, tile), runs of one fascicle
+    const size_t nct = (size_t)nc * T;
+    L.wc_ent.assign(nct + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) {
+        const int32_t v = voxel_of_dsc[p];
+        ++L.wc_ent[(size_t)vox_chunk[(size_t)v] * T + atom_v[p] / TA + 1];
+    }
+    for (size_t i = 0; i < nct; ++i) L.wc_ent[i + 1] += L.wc_ent[i];
+    std::vector<int32_t> next(L.wc_ent.begin(), L.wc_ent.end() - 1), erank((size_t)nnz);
+    L.wkey.assign((size_t)nnz, 0);
+    L.wphi.assign((size_t)nnz, 0.f);
+    for (int64_t j = 0; j < nnz; ++j) {
+        const int32_t p = wc_perm[j];
+        const int32_t v = voxel_of_dsc[p];
+        const int t = atom_v[p] / TA;
+        const int32_t e = next[(size_t)vox_chunk[(size_t)v] * T + t]++;
+        L.wkey[(size_t)e] = static_cast<uint16_t>(((atom_v[p] - t * TA) << 6) | vox_slot[(size_t)v]);
+        L.wphi[(size_t)e] = phi_v[p];
+        erank[(size_t)e] = fas_v[p];
+    }
+    // runs of one fascicle; each bucket cut into kChunkWaves wave ranges of about
+    // equal length at run starts
+    std::vector<int32_t> run_rank;
+    L.wc_wave.assign(nct * kChunkWaves + 1, 0);
+    L.wc_wrun.assign(nct * kChunkWaves, 0);
+    for (size_t ct = 0; ct < nct; ++ct) {
+        const int32_t e0 = L.wc_ent[ct], e1 = L.wc_ent[ct + 1], n = e1 - e0;
+        int w = 0;
+        for (int32_t e = e0; e < e1; ++e) {
+            if (e != e0 && erank[(size_t)e] == erank[(size_t)e - 1]) continue;
+            L.wkey[(size_t)e] |= kRunStart;
+            // waves w.. whose share starts at or before e begin here
+            while (w < kChunkWaves && (int64_t)(e - e0) * kChunkWaves >= (int64_t)w * n) {
+                L.wc_wave[ct * kChunkWaves + w] = e;
+                L.wc_wrun[ct * kChunkWaves + w] = static_cast<int32_t>(run_rank.size());
+                ++w;
+            }
+            run_rank.push_back(erank[(size_t)e]);
+        }
+        for (; w < kChunkWaves; ++w) {   // empty wave ranges at the bucket end
+            L.wc_wave[ct * kChunkWaves + w] = e1;
+            L.wc_wrun[ct * kChunkWaves + w] = static_cast<int32_t>(run_rank.size());
+        }
+    }
+    L.wc_wave[nct * kChunkWaves] = static_cast<int32_t>(nnz);
+    L.n_runs = (int64_t)run_rank.size();
+    // WC pass 2: each rank's runs in run order
+    L.rr_ptr.assign((size_t)nf + 1, 0);
+    for (int64_t r = 0; r < L.n_runs; ++r) ++L.rr_ptr[(size_t)run_rank[(size_t)r] + 1];
+    for (int r = 0; r < nf; ++r) L.rr_ptr[(size_t)r + 1] += L.rr_ptr[(size_t)r];
+    std::vector<int32_t> fill(L.rr_ptr.begin(), L.rr_ptr.end() - 1);
+    L.rr.assign((size_t)L.n_runs, 0);
+    for (int64_t r = 0; r < L.n_runs; ++r) L.rr[(size_t)fill[(size_t)run_rank[(size_t)r]]++] = static_cast<int32_t>(r);
+    return LIFE_OK;
 }
-
 std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePolicy policy)
 {
     const int n = static_cast<int>(work.size());
@@ -356,83 +520,6 @@ std::vector<int32_t> chunk_schedule(const std::vector<int64_t> &work, SchedulePo
     for (int x = 0; x < kXcds; ++x)
         for (int k = 0; k < bound[x + 1] - bound[x]; ++k) map[(size_t)k * kXcds + x] = bound[x] + k;
     return map;
-}
-
-int64_t chunked_arrays(const life_dims *d, const TileGeom &tg, int n_chunks, const int32_t *tile_ptr,
-                       const int32_t *chunk_vox, const int32_t *proc_pos, const int16_t *atom_v,
-                       const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
-                       const int32_t *wc_perm, std::vector<int32_t> &wave_work, std::vector<int16_t> &atom_c,
-                       std::vector<int32_t> &fas_c, std::vector<float> &phi_c, std::vector<int32_t> &z_pos,
-                       std::vector<int32_t> &wc_perm_z, std::vector<int32_t> &tile_z)
-{
-    const int T = tg.n_tiles;
-    wave_work.assign((size_t)n_chunks * T * kChunkWaves * kWorkInts, 0);
-    std::vector<int32_t> cpos((size_t)d->nnz);
-    const int64_t n_pad = chunk_layout(d, tg, tile_ptr, chunk_vox, n_chunks, wave_work.data(), cpos.data());
-    if (n_pad > kMaxNnz) return -1;
-    atom_c.assign((size_t)n_pad, 0);
-    fas_c.assign((size_t)n_pad, 0);
-    phi_c.assign((size_t)n_pad, 0.f);
-    for (int64_t p = 0; p < d->nnz; ++p) {
-        const size_t q = (size_t)cpos[(size_t)p];
-        atom_c[q] = atom_v[p];
-        fas_c[q] = fas_v[p];
-        phi_c[q] = phi_v[p];
-    }
-    // pads (the tail of each slot's sub-range) repeat the atom before them
-    for (int c = 0; c < n_chunks; ++c)
-        for (int t = 0; t < T; ++t)
-            for (int w = 0; w < kChunkWaves; ++w) {
-                const int32_t *ww = &wave_work[((size_t)(c * T + t) * kChunkWaves + w) * kWorkInts];
-                for (int j = 0; j < kWaveVoxels; ++j) {
-                    const int v = chunk_vox[(size_t)c * kChunkVoxels + w * kWaveVoxels + j];
-                    if (v < 0) continue;
-                    const int64_t beg = ww[0] + (int64_t)kStepEntries * (j ? ww[j] : 0);
-                    const int64_t end = ww[0] + (int64_t)kStepEntries * ww[j + 1];
-                    const int64_t n_real = tile_ptr[(size_t)v * (T + 1) + t + 1] - tile_ptr[(size_t)v * (T + 1) + t];
-                    for (int64_t q = beg + n_real; q < end; ++q) atom_c[(size_t)q] = atom_c[(size_t)q - 1];
-                }
-            }
-    // z order: inside each chunk's range, its entries by tile, in WC order inside a tile, then its pads
-    std::vector<int64_t> next((size_t)n_chunks + 1);
-    for (int c = 0; c < n_chunks; ++c) next[c] = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];
-    next[n_chunks] = n_pad;
-    const std::vector<int64_t> chunk_end(next.begin() + 1, next.end());
-    std::vector<int64_t> tnext((size_t)n_chunks * T, 0);
-    for (int64_t p = 0; p < d->nnz; ++p) {
-        const int32_t v = voxel_of_dsc[p];
-        const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
-        tnext[(size_t)c * T + atom_v[p] / tg.tile_atoms]++;
-    }
-    tile_z.assign((size_t)n_chunks * T * 2, 0);
-    for (int c = 0; c < n_chunks; ++c) {
-        int64_t b = next[c];
-        for (int t = 0; t < T; ++t) {
-            const int64_t n = tnext[(size_t)c * T + t];
-            tnext[(size_t)c * T + t] = b;
-            tile_z[2 * ((size_t)c * T + t)] = static_cast<int32_t>(b);
-            tile_z[2 * ((size_t)c * T + t) + 1] = static_cast<int32_t>(n);
-            b += n;
-        }
-        next[c] = b;   // pads follow the real entries
-    }
-    z_pos.assign((size_t)n_pad, -1);
-    wc_perm_z.resize((size_t)d->nnz);
-    for (int64_t j = 0; j < d->nnz; ++j) {
-        const int32_t p = wc_perm[j];
-        const int32_t v = voxel_of_dsc[p];
-        const int c = (proc_pos ? proc_pos[v] : v) / kChunkVoxels;
-        const int32_t zp = static_cast<int32_t>(tnext[(size_t)c * T + atom_v[p] / tg.tile_atoms]++);
-        z_pos[(size_t)cpos[(size_t)p]] = zp;
-        wc_perm_z[(size_t)j] = zp;
-    }
-    for (int c = 0; c < n_chunks; ++c) {
-        const int64_t cb = wave_work[((size_t)c * T * kChunkWaves) * kWorkInts];
-        for (int64_t q = cb; q < chunk_end[c]; ++q)
-            if (z_pos[(size_t)q] < 0) z_pos[(size_t)q] = static_cast<int32_t>(next[c]++);
-        if (next[c] != chunk_end[c]) return -1;   // layout inconsistency (cannot happen)
-    }
-    return n_pad;
 }
 
 }  // namespace life
