@@ -249,6 +249,19 @@ life_status life_dsc_ws(life_plan_t plan, const float *D, const float *w, float 
 life_status life_wc_ws(life_plan_t plan, const float *D, const float *y, float *g, void *scratch,
                        uint64_t scratch_bytes, void *stream);
 
+/* life_dsc for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and bitwise the same y, with the call's workspace (the weights in the
+ * plan's fascicle order, 4 * n_fascicles bytes rounded up to 256) in a static
+ * device array of 64 MiB that the library holds on each device it runs on until
+ * the process ends.  The call allocates and frees nothing and creates no events
+ * (the profiling hooks do not record it).  Every call on one device shares that
+ * device's array: calls that overlap in time on one device race (enqueue them on
+ * one stream, or order the streams).  Arguments as life_dsc.
+ * Errors: as life_dsc; LIFE_ERANGE when the workspace exceeds 64 MiB
+ * (n_fascicles above 16,777,216). */
+life_status life_dsc_noalloc(life_plan_t plan, const float *D, const float *w, float *y, void *stream);
+
 /* One SBB-NNLS iteration, Algorithm 1 (Sec. 2.1) with eqs. 5-6:
  *   r  = M w - b;   g = M^T r  (the gradient, eq. 6);
  *   g~ = g with g_f set to 0 where w_f = 0 and g_f > 0 (projected gradient);

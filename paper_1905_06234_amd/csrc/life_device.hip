@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <utility>
@@ -1236,12 +1237,20 @@ int slots_for(int nth)
     return 32;
 }
 
+// Set while a call that must not create events enqueues its launches.
+thread_local bool t_no_events = false;
+struct NoEvents {
+    bool prev;
+    NoEvents() : prev(t_no_events) { t_no_events = true; }
+    ~NoEvents() { t_no_events = prev; }
+};
+
 // Launch with optional event bracketing; returns the launch status.
 template <class F>
 life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool prof = p->profile;
+    const bool prof = p->profile && !t_no_events;
     if (prof) {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
         if (hipEventRecord(e0, s) != hipSuccess) return LIFE_EDEVICE;
@@ -2101,4 +2110,51 @@ extern "C" life_status life_profile_read(life_plan_t plan, double *ms, int64_t *
         if (count) count[k] = cnt[k];
     }
     return st;
+}
+
+// ============================================================================= allocation-free DSC
+
+namespace {
+
+// Scratch of life_dsc_noalloc: a file-scope device array, one copy per device,
+// held from the first use until the process ends.  Host code never passes this
+// symbol itself to a kernel (on the host it names a stand-in, not device memory);
+// it uses the device address hipGetSymbolAddress returns for each device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char noalloc_scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;
+char *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of noalloc_scratch on device dev (the current device), looked up
+// once per device.
+life_status noalloc_base(int dev, char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return LIFE_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !ptr) return LIFE_EDEVICE;
+        g_noalloc_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_noalloc_ptr[dev];
+    return LIFE_OK;
+}
+
+}  // namespace
+
+extern "C" life_status life_dsc_noalloc(life_plan_t plan, const float *D, const float *w, float *y, void *stream)
+{
+    if (!plan || !dsc_args_ok(plan, D, w, y)) return LIFE_EINVAL;
+    if (workspace_layout(plan, kWsDsc, nullptr, nullptr) > kNoAllocScratchBytes) return LIFE_ERANGE;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return LIFE_EDEVICE;
+    char *base = nullptr;
+    life_status st = noalloc_base(plan->device, &base);
+    if (st != LIFE_OK) return st;
+    Workspace ws;
+    workspace_layout(plan, kWsDsc, base, &ws);
+    NoEvents quiet;   // the profiling hooks would create events: not on this path
+    return dsc_call(plan, ws, D, w, y, static_cast<hipStream_t>(stream));
 }

@@ -65,6 +65,7 @@ _SIGS = {
     "life_dsc_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
     "life_wc_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
     "life_sbbnnls_step_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_uint64, _P]),
+    "life_dsc_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_sbbnnls_step_lagged": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "life_dict_grad": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "life_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -337,6 +338,12 @@ class Plan:
             _check("life_dsc", load().life_dsc(*args, _stream(stream, w.device)))
         else:
             _check("life_dsc_ws", load().life_dsc_ws(*args, *self._scratch(scratch), _stream(stream, w.device)))
+        return y
+
+    def dsc_noalloc(self, D, w, y, stream=None):
+        """y = M w into a given y with the library's static scratch (life_dsc_noalloc)."""
+        _check("life_dsc_noalloc", load().life_dsc_noalloc(self._h, self._d(D), _dev_f32(w, self.dims.n_fascicles, "w"),
+                                                           _dev_f32(y, self.n_signal, "y"), _stream(stream, w.device)))
         return y
 
     def wc(self, D, y, g=None, stream=None, scratch=None):
