@@ -100,6 +100,11 @@ typedef enum {
 /* Human-readable name of a status code (static string; never NULL). */
 const char *life_status_str(life_status s);
 
+/* The HIP runtime's message for the last device error that a kernel launch of
+ * this library ran into on the calling thread ("" if none): the detail behind a
+ * LIFE_EDEVICE (static string; never NULL). */
+const char *life_hip_error(void);
+
 /* Restructuring on the host only (no device touched): the data-restructuring
  * step of Sec. 4.1 ("Data Restructuring": voxel-based for DSC; fiber-based,
  * i.e. by fascicle, for WC) as two permutations with their segment offsets.
@@ -145,6 +150,36 @@ life_status life_plan(const life_dims *dims, const int16_t *atom, const int32_t 
 life_status life_plan_ex(const life_dims *dims, const int16_t *atom, const int32_t *voxel,
                          const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
                          life_plan_t *out);
+
+/* Flags of life_plan_flags. */
+enum {
+    LIFE_PLAN_DEVICE_INPUT = 1, /* atom, voxel, fascicle, phi are device pointers (else host) */
+    LIFE_PLAN_HOST_BUILD = 2    /* restructure on the host (the reference builder; slower)   */
+};
+
+/* Words written by life_plan_digest. */
+#define LIFE_DIGEST_WORDS 24
+
+/* The general plan builder (life_plan, life_plan_ex and life_plan_batch call it
+ * with flags = 0): n_inst = 1 builds a single problem (vox_off, fas_off may then
+ * be NULL), n_inst > 1 a batched plan as life_plan_batch.  The restructuring of
+ * Sec. 4.1 (the sorts by voxel and by fascicle and the chunked layout derived
+ * from them) runs on the device with stable radix sorts, scans and gathers, and
+ * gives the same plan, bit for bit, as the host builder (LIFE_PLAN_HOST_BUILD),
+ * which stays available as the reference.  With LIFE_PLAN_DEVICE_INPUT the COO
+ * arrays are device memory of the current device (not retained; nothing is
+ * copied from the host).  The host builder is also used when N_theta > 128 or a
+ * voxel crosses more than 16384 fascicles.  Synchronous.
+ * Errors: as life_plan_batch; LIFE_EINVAL for unknown flags. */
+life_status life_plan_flags(const life_dims *dims, int32_t n_inst, const int32_t *vox_off, const int32_t *fas_off,
+                            const int16_t *atom, const int32_t *voxel, const int32_t *fascicle, const float *phi,
+                            const int16_t *voxel_xyz, uint32_t flags, life_plan_t *out);
+
+/* Digest of every array of a plan (one 64-bit FNV-1a hash per array, the last
+ * word over the layout's sizes), to compare plans bit for bit.  digest: host,
+ * LIFE_DIGEST_WORDS entries.  Synchronous.  Errors: LIFE_EINVAL, LIFE_ENOMEM,
+ * LIFE_EDEVICE. */
+life_status life_plan_digest(life_plan_t plan, uint64_t *digest);
 
 /* A batched plan: n_inst independent problems that share the dictionary D,
  * given as one block-diagonal problem.  The caller concatenates the instances:

@@ -1237,6 +1237,10 @@ int slots_for(int nth)
     return 32;
 }
 
+// The last HIP runtime error a call of this thread ran into (life_hip_error).
+thread_local const char *t_hip_error = "";
+void note_hip_error(hipError_t e) { t_hip_error = hipGetErrorString(e); }
+
 // Set while a call that must not create events enqueues its launches.
 thread_local bool t_no_events = false;
 struct NoEvents {
@@ -1261,6 +1265,7 @@ life_status launch(life_plan_s *p, int kind, hipStream_t s, F &&f)
         if (hipEventRecord(e1, s) != hipSuccess) return LIFE_EDEVICE;
         p->events.push_back({kind, {e0, e1}});
     }
+    if (err != hipSuccess) note_hip_error(err);
     return err == hipSuccess ? LIFE_OK : LIFE_EDEVICE;
 }
 
@@ -1447,11 +1452,14 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
 
 namespace {
 
-// Plan construction shared by life_plan, life_plan_ex and life_plan_batch
-// (n_inst <= 1: a single problem).
-life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t *voxel, const int32_t *fascicle,
-                       const float *phi, const int16_t *voxel_xyz, int n_inst, const int32_t *vox_off,
-                       const int32_t *fas_off, life_plan_t *out)
+// Plan construction shared by life_plan, life_plan_ex, life_plan_batch and
+// life_plan_flags (n_inst <= 1: a single problem).  The restructuring runs on the
+// device (life::plan_gpu) unless LIFE_PLAN_HOST_BUILD asks for the host builder,
+// the tile geometry is not chunked (N_theta > 128), or a voxel crosses more
+// fascicles than a chunk holds; both builders give the same plan bit for bit.
+life_status build_plan(const life_dims *dims, const int16_t *atom_in, const int32_t *voxel_in,
+                       const int32_t *fascicle_in, const float *phi_in, const int16_t *voxel_xyz, int n_inst,
+                       const int32_t *vox_off, const int32_t *fas_off, uint32_t flags, life_plan_t *out)
 {
     if (!out) return LIFE_EINVAL;
     *out = nullptr;
@@ -1459,15 +1467,32 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     if (st != LIFE_OK) return st;
     if ((st = life::validate_coords(dims, voxel_xyz)) != LIFE_OK) return st;
     const life_dims d = *dims;
-    if (d.nnz > 0 && !phi) return LIFE_EINVAL;
+    if (d.nnz > 0 && (!phi_in || !atom_in || !voxel_in || !fascicle_in)) return LIFE_EINVAL;
+    const bool dev_in = (flags & LIFE_PLAN_DEVICE_INPUT) != 0;
     const bool batched = n_inst > 1;
     const int32_t one_v[2] = {0, d.n_voxels}, one_f[2] = {0, d.n_fascicles};
     if (!batched) {
         n_inst = 1;
         vox_off = one_v;
         fas_off = one_f;
+    } else {
+        if (vox_off[0] != 0 || fas_off[0] != 0 || vox_off[n_inst] != d.n_voxels || fas_off[n_inst] != d.n_fascicles)
+            return LIFE_EINVAL;
+        for (int k = 0; k < n_inst; ++k)
+            if (vox_off[k + 1] < vox_off[k] || fas_off[k + 1] < fas_off[k]) return LIFE_EINVAL;
     }
-    std::vector<int32_t> perm, vptr, wperm, fptr, rank, ext, ppos, pvox, vdsc;
+    const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
+    if (batched && tg.row_floats == 0) return LIFE_EINVAL;   // batched plans need N_theta <= 128
+    const int32_t n_pos = life::padded_positions(&d, n_inst, vox_off);
+    if (n_pos < 0) return LIFE_ERANGE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        // no device: still report bad host input as such
+        if (!dev_in && (st = life::validate_indices(&d, atom_in, voxel_in, fascicle_in)) != LIFE_OK) return st;
+        return LIFE_EDEVICE;
+    }
+
+    std::vector<int32_t> perm, vptr, wperm, fptr, rank, ext, ppos, pvox, vdsc, fas_inst;
     std::vector<int32_t> aptr, avox, afas, cmap;
     std::vector<float> aphi;
     std::vector<int16_t> atom_v;
@@ -1475,58 +1500,150 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     std::vector<float> phi_v;
     std::vector<int32_t> ichunk((size_t)n_inst + 1, 0);
     life::ChunkLayout L;
-    const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
-    if (batched) {
-        if (tg.row_floats == 0) return LIFE_EINVAL;   // batched plans need N_theta <= 128
-        if ((st = life::validate_indices(&d, atom, voxel, fascicle)) != LIFE_OK) return st;
-        if ((st = life::validate_instances(&d, n_inst, vox_off, fas_off, voxel, fascicle)) != LIFE_OK) return st;
-    }
-    const int32_t n_pos = life::padded_positions(&d, n_inst, vox_off);
-    if (n_pos < 0) return LIFE_ERANGE;
+    life::DevLayout G;   // device-built arrays (owned here until the plan takes them)
+    struct GFree {
+        life::DevLayout *g;
+        ~GFree() { life::free_dev_layout(g); }
+    } gfree{&G};
+    bool on_gpu = false;
     int n_chunks = 0;
+    std::vector<int32_t> bounds;
+    std::vector<int64_t> work;
+    int max_fas = 0;
+    int64_t n_pad = 0, n_runs = 0;
     try {
-        perm.resize((size_t)d.nnz);
-        wperm.resize((size_t)d.nnz);
-        vptr.resize((size_t)d.n_voxels + 1);
-        fptr.resize((size_t)d.n_fascicles + 1);
-        rank.resize((size_t)d.n_fascicles);
-        ext.resize((size_t)d.n_fascicles);
         ppos.resize((size_t)d.n_voxels);
         pvox.resize((size_t)n_pos);
         life::voxel_order(&d, voxel_xyz, n_inst, vox_off, ppos.data(), pvox.data());
-        std::vector<int32_t> fas_inst;
         if (batched) {
             // each instance's fascicles take one contiguous block of ranks
             fas_inst.resize((size_t)d.n_fascicles);
             for (int k = 0; k < n_inst; ++k)
                 for (int32_t f = fas_off[k]; f < fas_off[k + 1]; ++f) fas_inst[(size_t)f] = k;
         }
-        st = life::plan_host(&d, atom, voxel, fascicle, (voxel_xyz || batched) ? ppos.data() : nullptr, n_pos,
-                             batched ? fas_inst.data() : nullptr, perm.data(), vptr.data(), rank.data(),
-                             wperm.data(), fptr.data());
-        if (st != LIFE_OK) return st;
-        for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
-        atom_v.resize((size_t)d.nnz);
-        fas_v.resize((size_t)d.nnz);
-        phi_v.resize((size_t)d.nnz);
-        vdsc.resize((size_t)d.nnz);
-        for (int64_t p = 0; p < d.nnz; ++p) {
-            const int32_t c = perm[(size_t)p];
-            atom_v[(size_t)p] = atom[c];
-            fas_v[(size_t)p] = rank[(size_t)fascicle[c]];
-            phi_v[(size_t)p] = phi[c];
-            vdsc[(size_t)p] = voxel[c];
-        }
-        if (tg.row_floats > 0) {
-            st = life::chunk_layout(&d, tg, vptr.data(), atom_v.data(), fas_v.data(), phi_v.data(), vdsc.data(),
-                                    wperm.data(), ppos.data(), pvox.data(), n_pos, &L);
-            if (st != LIFE_OK) return st;
-            if (L.fas_overflow) {
-                // a voxel crosses more fascicles than a chunk can hold: generic kernels
-                if (batched) return LIFE_EINVAL;
-                L = life::ChunkLayout();
+        const int32_t *ppos_used = (voxel_xyz || batched) ? ppos.data() : nullptr;
+        if (!(flags & LIFE_PLAN_HOST_BUILD) && tg.row_floats > 0) {
+            // the COO arrays on the device
+            const int16_t *atom = atom_in;
+            const int32_t *voxel = voxel_in, *fascicle = fascicle_in;
+            const float *phi = phi_in;
+            void *stage[4] = {nullptr, nullptr, nullptr, nullptr};
+            struct SFree {
+                void **s;
+                ~SFree() { for (int i = 0; i < 4; ++i) if (s[i]) (void)hipFree(s[i]); }
+            } sfree{stage};
+            if (!dev_in && d.nnz > 0) {
+                const size_t sz[4] = {sizeof(int16_t), sizeof(int32_t), sizeof(int32_t), sizeof(float)};
+                const void *src[4] = {atom_in, voxel_in, fascicle_in, phi_in};
+                for (int i = 0; i < 4; ++i) {
+                    hipError_t e = hipMalloc(&stage[i], sz[i] * (size_t)d.nnz);
+                    if (e == hipSuccess) e = hipMemcpy(stage[i], src[i], sz[i] * (size_t)d.nnz, hipMemcpyHostToDevice);
+                    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LIFE_ENOMEM : LIFE_EDEVICE;
+                }
+                atom = static_cast<const int16_t *>(stage[0]);
+                voxel = static_cast<const int32_t *>(stage[1]);
+                fascicle = static_cast<const int32_t *>(stage[2]);
+                phi = static_cast<const float *>(stage[3]);
             }
-            n_chunks = L.n_chunks;
+            st = life::plan_gpu(&d, tg, atom, voxel, fascicle, phi, ppos_used, pvox.data(), n_pos,
+                                batched ? fas_inst.data() : nullptr, vox_off, n_inst, &G);
+            if (st == LIFE_OK && hipGetLastError() != hipSuccess) st = LIFE_EDEVICE;
+            if (st != LIFE_OK) return st;
+            if (G.fas_overflow) {
+                if (batched) return LIFE_EINVAL;
+                life::free_dev_layout(&G);   // the host builder makes the generic plan below
+            } else {
+                on_gpu = true;
+                n_chunks = G.n_chunks;
+                bounds = G.bounds;
+                work = G.work;
+                max_fas = G.max_fas;
+                n_pad = G.n_pad;
+                n_runs = G.n_runs;
+            }
+        }
+        if (!on_gpu) {
+            // host builder: host copies of the COO arrays when they are on the device
+            std::vector<int16_t> atom_h;
+            std::vector<int32_t> voxel_h, fascicle_h;
+            std::vector<float> phi_h;
+            const int16_t *atom = atom_in;
+            const int32_t *voxel = voxel_in, *fascicle = fascicle_in;
+            const float *phi = phi_in;
+            if (dev_in && d.nnz > 0) {
+                atom_h.resize((size_t)d.nnz);
+                voxel_h.resize((size_t)d.nnz);
+                fascicle_h.resize((size_t)d.nnz);
+                phi_h.resize((size_t)d.nnz);
+                hipError_t e = hipMemcpy(atom_h.data(), atom_in, sizeof(int16_t) * d.nnz, hipMemcpyDeviceToHost);
+                if (e == hipSuccess) e = hipMemcpy(voxel_h.data(), voxel_in, sizeof(int32_t) * d.nnz, hipMemcpyDeviceToHost);
+                if (e == hipSuccess)
+                    e = hipMemcpy(fascicle_h.data(), fascicle_in, sizeof(int32_t) * d.nnz, hipMemcpyDeviceToHost);
+                if (e == hipSuccess) e = hipMemcpy(phi_h.data(), phi_in, sizeof(float) * d.nnz, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return LIFE_EDEVICE;
+                atom = atom_h.data();
+                voxel = voxel_h.data();
+                fascicle = fascicle_h.data();
+                phi = phi_h.data();
+            }
+            if (batched) {
+                if ((st = life::validate_indices(&d, atom, voxel, fascicle)) != LIFE_OK) return st;
+                if ((st = life::validate_instances(&d, n_inst, vox_off, fas_off, voxel, fascicle)) != LIFE_OK)
+                    return st;
+            }
+            perm.resize((size_t)d.nnz);
+            wperm.resize((size_t)d.nnz);
+            vptr.resize((size_t)d.n_voxels + 1);
+            fptr.resize((size_t)d.n_fascicles + 1);
+            rank.resize((size_t)d.n_fascicles);
+            ext.resize((size_t)d.n_fascicles);
+            st = life::plan_host(&d, atom, voxel, fascicle, ppos_used, n_pos, batched ? fas_inst.data() : nullptr,
+                                 perm.data(), vptr.data(), rank.data(), wperm.data(), fptr.data());
+            if (st != LIFE_OK) return st;
+            for (int32_t f = 0; f < d.n_fascicles; ++f) ext[(size_t)rank[(size_t)f]] = f;
+            atom_v.resize((size_t)d.nnz);
+            fas_v.resize((size_t)d.nnz);
+            phi_v.resize((size_t)d.nnz);
+            vdsc.resize((size_t)d.nnz);
+            for (int64_t q = 0; q < d.nnz; ++q) {
+                const int32_t c = perm[(size_t)q];
+                atom_v[(size_t)q] = atom[c];
+                fas_v[(size_t)q] = rank[(size_t)fascicle[c]];
+                phi_v[(size_t)q] = phi[c];
+                vdsc[(size_t)q] = voxel[c];
+            }
+            if (tg.row_floats > 0) {
+                st = life::chunk_layout(&d, tg, vptr.data(), atom_v.data(), fas_v.data(), phi_v.data(), vdsc.data(),
+                                        wperm.data(), ppos.data(), pvox.data(), n_pos, &L);
+                if (st != LIFE_OK) return st;
+                if (L.fas_overflow) {
+                    // a voxel crosses more fascicles than a chunk can hold: generic kernels
+                    if (batched) return LIFE_EINVAL;
+                    L = life::ChunkLayout();
+                }
+                n_chunks = L.n_chunks;
+                bounds = L.bounds;
+                work = L.work;
+                max_fas = L.max_fas;
+                n_pad = L.n_pad;
+                n_runs = L.n_runs;
+            }
+            if (n_chunks == 0 && d.nnz > 0) {
+                // atom-major copy of the nonzeros for the generic dictionary gradient
+                aptr.assign((size_t)d.n_atoms + 1, 0);
+                for (int64_t q = 0; q < d.nnz; ++q) ++aptr[(size_t)atom_v[(size_t)q] + 1];
+                for (int32_t a = 0; a < d.n_atoms; ++a) aptr[(size_t)a + 1] += aptr[(size_t)a];
+                std::vector<int32_t> fill(aptr.begin(), aptr.end() - 1);
+                avox.resize((size_t)d.nnz);
+                afas.resize((size_t)d.nnz);
+                aphi.resize((size_t)d.nnz);
+                for (int64_t q = 0; q < d.nnz; ++q) {
+                    const int32_t e = fill[(size_t)atom_v[(size_t)q]]++;
+                    avox[(size_t)e] = vdsc[(size_t)q];
+                    afas[(size_t)e] = fas_v[(size_t)q];
+                    aphi[(size_t)e] = phi_v[(size_t)q];
+                }
+            }
         }
         if (batched) {
             // first chunk of each instance: instance blocks are whole groups of positions
@@ -1534,27 +1651,11 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             size_t c = 0;
             for (int k = 0; k < n_inst; ++k) {
                 base += cdiv(vox_off[k + 1] - vox_off[k], kChunkVoxels) * kChunkVoxels;
-                while (c < L.bounds.size() && L.bounds[c] < base) ++c;
+                while (c < bounds.size() && bounds[c] < base) ++c;
                 ichunk[(size_t)k + 1] = static_cast<int32_t>(c);
             }
         } else {
             ichunk[1] = n_chunks;
-        }
-        if (n_chunks == 0 && d.nnz > 0) {
-            // atom-major copy of the nonzeros for the generic dictionary gradient
-            aptr.assign((size_t)d.n_atoms + 1, 0);
-            for (int64_t q = 0; q < d.nnz; ++q) ++aptr[(size_t)atom_v[(size_t)q] + 1];
-            for (int32_t a = 0; a < d.n_atoms; ++a) aptr[(size_t)a + 1] += aptr[(size_t)a];
-            std::vector<int32_t> fill(aptr.begin(), aptr.end() - 1);
-            avox.resize((size_t)d.nnz);
-            afas.resize((size_t)d.nnz);
-            aphi.resize((size_t)d.nnz);
-            for (int64_t q = 0; q < d.nnz; ++q) {
-                const int32_t e = fill[(size_t)atom_v[(size_t)q]]++;
-                avox[(size_t)e] = vdsc[(size_t)q];
-                afas[(size_t)e] = fas_v[(size_t)q];
-                aphi[(size_t)e] = phi_v[(size_t)q];
-            }
         }
         if (n_chunks > 0) {
             // one grid length for every schedule policy (the longest map, the others
@@ -1562,8 +1663,8 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
             // grid of launches already captured in a graph
             size_t grid = 0;
             for (int pol : {life::kScheduleIndex, life::kScheduleXcdCount, life::kScheduleXcdWork})
-                grid = std::max(grid, life::chunk_schedule(L.work, (life::SchedulePolicy)pol).size());
-            cmap = life::chunk_schedule(L.work, life::kScheduleDefault);
+                grid = std::max(grid, life::chunk_schedule(work, (life::SchedulePolicy)pol).size());
+            cmap = life::chunk_schedule(work, life::kScheduleDefault);
             cmap.resize(grid, -1);
         }
     } catch (const std::bad_alloc &) {
@@ -1573,18 +1674,15 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     life_plan_s *p = new (std::nothrow) life_plan_s;
     if (!p) return LIFE_ENOMEM;
     p->dims = d;
-    if (hipGetDevice(&p->device) != hipSuccess) {
-        delete p;
-        return LIFE_EDEVICE;
-    }
+    p->device = dev;
     p->slots = slots_for(d.n_theta);
     p->tile = tg;
     p->n_chunks = n_chunks;
-    p->n_pad = L.n_pad;
+    p->n_pad = n_pad;
     p->chunk_grid = (int)cmap.size();
-    p->chunk_work = L.work;
-    p->max_fas = L.max_fas;
-    p->n_runs = L.n_runs;
+    p->chunk_work = work;
+    p->max_fas = max_fas;
+    p->n_runs = n_runs;
     const int64_t nb = std::max<int64_t>({cdiv(d.n_voxels, kSegPerBlock), (int64_t)n_chunks,
                                           cdiv(d.n_fascicles, kFasPerBlock), cdiv(d.n_fascicles, kBlock), 1});
     p->part_stride = nb;
@@ -1624,29 +1722,43 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
     }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(dalloc(&p->vox_ptr, d.n_voxels + 1));
-    chk(dalloc(&p->atom_v, d.nnz));
-    chk(dalloc(&p->fas_v, d.nnz));
-    chk(dalloc(&p->phi_v, d.nnz));
-    chk(dalloc(&p->chunk_vox, (int64_t)L.chunk_vox.size()));
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) chk(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    // dst <- the device-built array (taken over), or a new copy of the host array
+    auto take = [&](auto **dst, auto *&dev_src, const auto &host_src) {
+        if (on_gpu) {
+            *dst = dev_src;
+            dev_src = nullptr;
+        } else {
+            chk(dalloc(dst, (int64_t)host_src.size()));
+            up(*dst, host_src.data(), sizeof(host_src[0]) * host_src.size());
+        }
+    };
+    take(&p->vox_ptr, G.vox_ptr, vptr);
+    take(&p->atom_v, G.atom_v, atom_v);
+    take(&p->fas_v, G.fas_v, fas_v);
+    take(&p->phi_v, G.phi_v, phi_v);
+    take(&p->fas_rank, G.fas_rank, rank);
+    take(&p->fas_ext, G.fas_ext, ext);
+    take(&p->fas_ptr, G.fas_ptr, fptr);
+    take(&p->wc_perm, G.wc_perm, wperm);
+    take(&p->chunk_vox, G.chunk_vox, L.chunk_vox);
+    take(&p->wave_work, G.wave_work, L.wave_work);
+    take(&p->atom_c, G.atom_c, L.atom_c);
+    take(&p->fas_c, G.fas_c, L.fas_c);
+    take(&p->loc_c, G.loc_c, L.loc_c);
+    take(&p->phi_c, G.phi_c, L.phi_c);
+    take(&p->cfas_ptr, G.cfas_ptr, L.cfas_ptr);
+    take(&p->cfas, G.cfas, L.cfas);
+    take(&p->wkey, G.wkey, L.wkey);
+    take(&p->wphi, G.wphi, L.wphi);
+    take(&p->wc_wave, G.wc_wave, L.wc_wave);
+    take(&p->wc_wrun, G.wc_wrun, L.wc_wrun);
+    take(&p->rr_ptr, G.rr_ptr, L.rr_ptr);
+    take(&p->rr, G.rr, L.rr);
     chk(dalloc(&p->chunk_map, (int64_t)cmap.size()));
-    chk(dalloc(&p->wave_work, (int64_t)L.wave_work.size()));
-    chk(dalloc(&p->atom_c, (int64_t)L.atom_c.size()));
-    chk(dalloc(&p->fas_c, (int64_t)L.fas_c.size()));
-    chk(dalloc(&p->loc_c, (int64_t)L.loc_c.size()));
-    chk(dalloc(&p->phi_c, (int64_t)L.phi_c.size()));
-    chk(dalloc(&p->cfas_ptr, (int64_t)L.cfas_ptr.size()));
-    chk(dalloc(&p->cfas, (int64_t)L.cfas.size()));
-    chk(dalloc(&p->wkey, (int64_t)L.wkey.size()));
-    chk(dalloc(&p->wphi, (int64_t)L.wphi.size()));
-    chk(dalloc(&p->wc_wave, (int64_t)L.wc_wave.size()));
-    chk(dalloc(&p->wc_wrun, (int64_t)L.wc_wrun.size()));
-    chk(dalloc(&p->rr_ptr, (int64_t)L.rr_ptr.size()));
-    chk(dalloc(&p->rr, (int64_t)L.rr.size()));
-    chk(dalloc(&p->fas_rank, d.n_fascicles));
-    chk(dalloc(&p->fas_ext, d.n_fascicles));
-    chk(dalloc(&p->fas_ptr, d.n_fascicles + 1));
-    chk(dalloc(&p->wc_perm, d.nnz));
+    up(p->chunk_map, cmap.data(), sizeof(int32_t) * cmap.size());
     {
         char *base = nullptr;
         chk(dalloc(&base, (int64_t)workspace_layout(p, kWsAll, nullptr, nullptr)));
@@ -1665,33 +1777,6 @@ life_status build_plan(const life_dims *dims, const int16_t *atom, const int32_t
         free_plan(p);
         return e == hipErrorOutOfMemory ? LIFE_ENOMEM : LIFE_EDEVICE;
     }
-    auto up = [&](void *dst, const void *src, size_t bytes) {
-        if (bytes) chk(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
-    };
-    up(p->vox_ptr, vptr.data(), sizeof(int32_t) * vptr.size());
-    up(p->atom_v, atom_v.data(), sizeof(int16_t) * atom_v.size());
-    up(p->fas_v, fas_v.data(), sizeof(int32_t) * fas_v.size());
-    up(p->phi_v, phi_v.data(), sizeof(float) * phi_v.size());
-    auto upv = [&](void *dst, const auto &v) { up(dst, v.data(), sizeof(v[0]) * v.size()); };
-    upv(p->chunk_vox, L.chunk_vox);
-    upv(p->chunk_map, cmap);
-    upv(p->wave_work, L.wave_work);
-    upv(p->atom_c, L.atom_c);
-    upv(p->fas_c, L.fas_c);
-    upv(p->loc_c, L.loc_c);
-    upv(p->phi_c, L.phi_c);
-    upv(p->cfas_ptr, L.cfas_ptr);
-    upv(p->cfas, L.cfas);
-    upv(p->wkey, L.wkey);
-    upv(p->wphi, L.wphi);
-    upv(p->wc_wave, L.wc_wave);
-    upv(p->wc_wrun, L.wc_wrun);
-    upv(p->rr_ptr, L.rr_ptr);
-    upv(p->rr, L.rr);
-    up(p->fas_rank, rank.data(), sizeof(int32_t) * rank.size());
-    up(p->fas_ext, ext.data(), sizeof(int32_t) * ext.size());
-    up(p->fas_ptr, fptr.data(), sizeof(int32_t) * fptr.size());
-    up(p->wc_perm, wperm.data(), sizeof(int32_t) * wperm.size());
     up(p->a_ptr, aptr.data(), sizeof(int32_t) * aptr.size());
     up(p->a_vox, avox.data(), sizeof(int32_t) * avox.size());
     up(p->a_fas, afas.data(), sizeof(int32_t) * afas.size());
@@ -1713,7 +1798,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
                                     const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
                                     life_plan_t *out)
 {
-    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, 1, nullptr, nullptr, out);
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, 1, nullptr, nullptr, 0, out);
 }
 
 extern "C" life_status life_plan_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
@@ -1722,7 +1807,98 @@ extern "C" life_status life_plan_batch(const life_dims *dims, int32_t n_inst, co
                                        life_plan_t *out)
 {
     if (n_inst < 1 || !vox_off || !fas_off) return LIFE_EINVAL;
-    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, out);
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, 0, out);
+}
+
+extern "C" life_status life_plan_flags(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                                       const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                                       const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                                       uint32_t flags, life_plan_t *out)
+{
+    if (n_inst < 1 || (n_inst > 1 && (!vox_off || !fas_off))) return LIFE_EINVAL;
+    if (flags & ~(uint32_t)(LIFE_PLAN_DEVICE_INPUT | LIFE_PLAN_HOST_BUILD)) return LIFE_EINVAL;
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, flags, out);
+}
+
+namespace {
+
+// FNV-1a over bytes, continued from h
+uint64_t fnv1a(uint64_t h, const void *data, size_t bytes)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" life_status life_plan_digest(life_plan_t plan, uint64_t *digest)
+{
+    if (!plan || !digest) return LIFE_EINVAL;
+    DeviceGuard g(plan->device);
+    if (!g.ok) return LIFE_EDEVICE;
+    const life_plan_s &p = *plan;
+    const life_dims &d = p.dims;
+    const int T = p.tile.n_tiles;
+    const int64_t nct = (int64_t)p.n_chunks * T;
+    struct Arr {
+        const void *ptr;
+        int64_t bytes;
+    };
+    const Arr arrs[LIFE_DIGEST_WORDS - 1] = {
+        {p.vox_ptr, 4 * ((int64_t)d.n_voxels + 1)},
+        {p.atom_v, 2 * d.nnz},
+        {p.fas_v, 4 * d.nnz},
+        {p.phi_v, 4 * d.nnz},
+        {p.fas_rank, 4 * (int64_t)d.n_fascicles},
+        {p.fas_ext, 4 * (int64_t)d.n_fascicles},
+        {p.fas_ptr, 4 * ((int64_t)d.n_fascicles + 1)},
+        {p.wc_perm, 4 * d.nnz},
+        {p.chunk_vox, 4 * (int64_t)p.n_chunks * kChunkVoxels},
+        {p.wave_work, 4 * nct * kChunkWaves * life::kWorkInts},
+        {p.atom_c, 2 * p.n_pad},
+        {p.fas_c, 4 * p.n_pad},
+        {p.loc_c, 2 * p.n_pad},
+        {p.phi_c, 4 * p.n_pad},
+        {p.cfas_ptr, p.n_chunks > 0 ? 4 * ((int64_t)p.n_chunks + 1) : 0},
+        {p.cfas, 0},   // length from cfas_ptr below
+        {p.wkey, p.n_chunks > 0 ? 2 * d.nnz : 0},
+        {p.wphi, p.n_chunks > 0 ? 4 * d.nnz : 0},
+        {p.wc_wave, p.n_chunks > 0 ? 4 * (nct * kChunkWaves + 1) : 0},
+        {p.wc_wrun, 4 * nct * kChunkWaves},
+        {p.rr_ptr, p.n_chunks > 0 ? 4 * ((int64_t)d.n_fascicles + 1) : 0},
+        {p.rr, 4 * p.n_runs},
+        {p.chunk_map, 4 * (int64_t)p.chunk_grid},
+    };
+    int64_t n_cfas = 0;
+    if (p.n_chunks > 0 && p.cfas_ptr) {
+        int32_t last = 0;
+        if (hipMemcpy(&last, p.cfas_ptr + p.n_chunks, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return LIFE_EDEVICE;
+        n_cfas = last;
+    }
+    std::vector<unsigned char> buf;
+    for (int i = 0; i < LIFE_DIGEST_WORDS - 1; ++i) {
+        const int64_t bytes = i == 15 ? 4 * n_cfas : arrs[i].bytes;
+        uint64_t h = 1469598103934665603ull;
+        if (bytes > 0 && arrs[i].ptr) {
+            try {
+                buf.resize((size_t)bytes);
+            } catch (const std::bad_alloc &) {
+                return LIFE_ENOMEM;
+            }
+            if (hipMemcpy(buf.data(), arrs[i].ptr, (size_t)bytes, hipMemcpyDeviceToHost) != hipSuccess)
+                return LIFE_EDEVICE;
+            h = fnv1a(h, buf.data(), (size_t)bytes);
+        }
+        digest[i] = h;
+    }
+    const int64_t scal[5] = {p.n_chunks, p.n_pad, p.n_runs, p.max_fas, p.chunk_grid};
+    digest[LIFE_DIGEST_WORDS - 1] = fnv1a(1469598103934665603ull, scal, sizeof(scal));
+    return LIFE_OK;
 }
 
 extern "C" life_status life_plan_destroy(life_plan_t plan)
@@ -2158,3 +2334,5 @@ extern "C" life_status life_dsc_noalloc(life_plan_t plan, const float *D, const 
     NoEvents quiet;   // the profiling hooks would create events: not on this path
     return dsc_call(plan, ws, D, w, y, static_cast<hipStream_t>(stream));
 }
+
+extern "C" const char *life_hip_error(void) { return t_hip_error; }

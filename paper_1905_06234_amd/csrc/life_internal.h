@@ -131,6 +131,41 @@ struct ChunkLayout {
     std::vector<int32_t> rr_ptr, rr;
 };
 
+// Voxel slots of chunks with the given position bounds (longest voxel first, ties
+// in processing order, each to the least loaded wave with a free slot):
+// chunk_vox [n_chunks * kChunkVoxels] (-1 = empty), and for every voxel its chunk
+// and slot (vox_chunk, vox_slot: -1 for voxels in no chunk).
+void chunk_slots(const life_dims *d, const int32_t *vox_ptr, const int32_t *proc_vox, const std::vector<int32_t> &bounds,
+                 std::vector<int32_t> &chunk_vox, std::vector<int32_t> &vox_chunk, std::vector<int32_t> &vox_slot);
+
+// The same restructuring on the device (life_plan_gpu.hip), from device COO arrays.
+// Produces the canonical DSC and WC orders and the chunked layout of ChunkLayout
+// (bit for bit what plan_host and chunk_layout give), in device memory that the
+// caller takes over.  With n_chunks = 0 on return (tile geometry not chunked, or a
+// voxel crossing more than kChunkFasCap fascicles) only the canonical orders are
+// built.
+struct DevLayout {
+    int32_t *vox_ptr = nullptr, *fas_v = nullptr, *fas_rank = nullptr, *fas_ext = nullptr, *fas_ptr = nullptr,
+            *wc_perm = nullptr, *vox_dsc = nullptr;
+    int16_t *atom_v = nullptr;
+    float *phi_v = nullptr;
+    int n_chunks = 0;
+    int64_t n_pad = 0, n_runs = 0;
+    int max_fas = 0;
+    bool fas_overflow = false;
+    std::vector<int32_t> bounds;
+    std::vector<int64_t> work;
+    int32_t *chunk_vox = nullptr, *wave_work = nullptr, *fas_c = nullptr, *cfas_ptr = nullptr, *cfas = nullptr,
+            *wc_wave = nullptr, *wc_wrun = nullptr, *rr_ptr = nullptr, *rr = nullptr;
+    int16_t *atom_c = nullptr;
+    uint16_t *loc_c = nullptr, *wkey = nullptr;
+    float *phi_c = nullptr, *wphi = nullptr;
+};
+void free_dev_layout(DevLayout *L);
+life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom, const int32_t *voxel,
+                     const int32_t *fascicle, const float *phi, const int32_t *proc_pos, const int32_t *proc_vox,
+                     int32_t n_pos, const int32_t *fas_inst, const int32_t *vox_off, int n_inst, DevLayout *out);
+
 // The chunked layout from the canonical DSC-order arrays (atom_v, fas_v = ranks,
 // phi_v, voxel of each DSC position), the WC permutation (wc_perm), the segment
 // offsets vox_ptr and the processing order (proc_pos / proc_vox over n_pos

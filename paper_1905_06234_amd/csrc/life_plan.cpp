@@ -277,6 +277,39 @@ int distinct_fascicles(const int32_t *vox_ptr, const int32_t *fas_v, const int32
 
 }  // namespace
 
+void chunk_slots(const life_dims *d, const int32_t *vox_ptr, const int32_t *proc_vox, const std::vector<int32_t> &bounds,
+                 std::vector<int32_t> &chunk_vox, std::vector<int32_t> &vox_chunk, std::vector<int32_t> &vox_slot)
+{
+    const int nc = (int)bounds.size() - 1;
+    chunk_vox.assign((size_t)nc * kChunkVoxels, -1);
+    vox_chunk.assign((size_t)d->n_voxels, -1);
+    vox_slot.assign((size_t)d->n_voxels, -1);
+    std::vector<int> ids;
+    for (int c = 0; c < nc; ++c) {
+        ids.clear();
+        for (int32_t k = bounds[c]; k < bounds[c + 1]; ++k) {
+            const int v = proc_vox ? proc_vox[k] : k;
+            if (v >= 0) ids.push_back(v);
+        }
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+            return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
+        });
+        int64_t load[kChunkWaves] = {0};
+        int fill[kChunkWaves] = {0};
+        int32_t *slots = chunk_vox.data() + (size_t)c * kChunkVoxels;
+        for (int v : ids) {
+            int best = -1;
+            for (int wv = 0; wv < kChunkWaves; ++wv)
+                if (fill[wv] < kWaveVoxels && (best < 0 || load[wv] < load[best])) best = wv;
+            const int slot = best * kWaveVoxels + fill[best]++;
+            slots[slot] = v;
+            vox_chunk[(size_t)v] = c;
+            vox_slot[(size_t)v] = slot;
+            load[best] += vox_ptr[v + 1] - vox_ptr[v];
+        }
+    }
+}
+
 life_status chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *vox_ptr, const int16_t *atom_v,
                          const int32_t *fas_v, const float *phi_v, const int32_t *voxel_of_dsc,
                          const int32_t *wc_perm, const int32_t *proc_pos, const int32_t *proc_vox, int32_t n_pos,
@@ -321,33 +354,8 @@ life_status chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *
     }
     const int nc = (int)L.bounds.size() - 1;
     L.n_chunks = nc;
-    // voxel slots of each chunk (longest first; ties keep processing order)
-    L.chunk_vox.assign((size_t)nc * kChunkVoxels, -1);
-    std::vector<int32_t> vox_chunk((size_t)nv, -1), vox_slot((size_t)nv, -1);
-    std::vector<int> ids;
-    for (int c = 0; c < nc; ++c) {
-        ids.clear();
-        for (int32_t k = L.bounds[c]; k < L.bounds[c + 1]; ++k) {
-            const int v = proc_vox ? proc_vox[k] : k;
-            if (v >= 0) ids.push_back(v);
-        }
-        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
-            return vox_ptr[a + 1] - vox_ptr[a] > vox_ptr[b + 1] - vox_ptr[b];
-        });
-        int64_t load[kChunkWaves] = {0};
-        int fill[kChunkWaves] = {0};
-        int32_t *slots = L.chunk_vox.data() + (size_t)c * kChunkVoxels;
-        for (int v : ids) {
-            int best = -1;
-            for (int wv = 0; wv < kChunkWaves; ++wv)
-                if (fill[wv] < kWaveVoxels && (best < 0 || load[wv] < load[best])) best = wv;
-            const int slot = best * kWaveVoxels + fill[best]++;
-            slots[slot] = v;
-            vox_chunk[(size_t)v] = c;
-            vox_slot[(size_t)v] = slot;
-            load[best] += vox_ptr[v + 1] - vox_ptr[v];
-        }
-    }
+    std::vector<int32_t> vox_chunk, vox_slot;
+    chunk_slots(d, vox_ptr, proc_vox, L.bounds, L.chunk_vox, vox_chunk, vox_slot);
     // padded positions of the DSC entries and the wave ranges
     L.wave_work.assign((size_t)nc * T * kChunkWaves * kWorkInts, 0);
     std::vector<int32_t> cpos((size_t)nnz);

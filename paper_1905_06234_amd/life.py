@@ -23,6 +23,9 @@ KERNELS = ("dsc", "wc_z", "wc_sum", "mask", "alpha", "update", "wc_z_2nd", "wc_s
            "dd_reduce")
 STATUS = {0: "LIFE_OK", 1: "LIFE_EINVAL", 2: "LIFE_ERANGE", 3: "LIFE_ENOMEM", 4: "LIFE_EDEVICE"}
 STATE_FIELDS = ("iter", "alpha", "obj", "gt_norm2", "num", "den")
+PLAN_DEVICE_INPUT = 1   # life_plan_flags: the COO arrays are device memory
+PLAN_HOST_BUILD = 2     # life_plan_flags: restructure on the host (the reference builder)
+DIGEST_WORDS = 24
 
 
 class LifeError(RuntimeError):
@@ -45,12 +48,16 @@ _lib = None
 _P = ctypes.c_void_p
 _SIGS = {
     "life_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "life_hip_error": (ctypes.c_char_p, []),
     "life_plan_host": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "life_plan": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "life_plan_ex": (ctypes.c_int, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "life_plan_batch": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
                                        ctypes.POINTER(_P)]),
     "life_plan_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "life_plan_flags": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                       ctypes.c_uint32, ctypes.POINTER(_P)]),
+    "life_plan_digest": (ctypes.c_int, [_P, _P]),
     "life_plan_host_batch": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
                                             _P, _P, _P, _P]),
     "life_plan_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -90,7 +97,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 
 def _check(fn: str, status: int):
     if status != 0:
-        raise LifeError(fn, status)
+        detail = load().life_hip_error().decode() if status == 4 else ""
+        raise LifeError(fn, status, detail)
 
 
 def _np_ptr(a: Optional[np.ndarray]):
@@ -239,7 +247,7 @@ class Plan:
         self.device = _torch().cuda.current_device()
 
     @classmethod
-    def batch(cls, instances, morton: bool = True) -> "Plan":
+    def batch(cls, instances, morton: bool = True, host_build: bool = False) -> "Plan":
         """A batched plan (life_plan_batch) of problems sharing one dictionary.
 
         instances: objects with n_theta, n_atoms, n_voxels, n_fascicles, atom,
@@ -251,10 +259,15 @@ class Plan:
         self = cls.__new__(cls)
         self.dims = dims
         self._h = ctypes.c_void_p()
-        _check("life_plan_batch", load().life_plan_batch(ctypes.byref(self.dims), n_inst, _np_ptr(vox_off),
-                                                         _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
-                                                         _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz),
-                                                         ctypes.byref(self._h)))
+        if host_build:
+            _check("life_plan_flags", load().life_plan_flags(
+                ctypes.byref(self.dims), n_inst, _np_ptr(vox_off), _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
+                _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz), PLAN_HOST_BUILD, ctypes.byref(self._h)))
+        else:
+            _check("life_plan_batch", load().life_plan_batch(ctypes.byref(self.dims), n_inst, _np_ptr(vox_off),
+                                                             _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
+                                                             _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz),
+                                                             ctypes.byref(self._h)))
         self.device = _torch().cuda.current_device()
         self.vox_off, self.fas_off = vox_off, fas_off
         return self
@@ -284,6 +297,41 @@ class Plan:
                                               _dev_f32(w, self.dims.n_fascicles, "w"),
                                               ctypes.c_void_p(states.data_ptr()), _stream(stream, w.device)))
         return w
+
+    @classmethod
+    def build(cls, n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle, phi,
+              voxel_xyz=None, host_build: bool = False, device_input: bool = False) -> "Plan":
+        """A single-problem plan through life_plan_flags.  host_build: restructure on
+        the host (the reference builder).  device_input: move atom, voxel, fascicle
+        and phi to the current device first and pass device pointers."""
+        torch = _torch()
+        xyz = _xyz(voxel_xyz, n_voxels)
+        atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+        phi = np.ascontiguousarray(phi, dtype=np.float32)
+        if phi.shape != atom.shape:
+            raise ValueError("phi must have one value per nonzero")
+        self = cls.__new__(cls)
+        self.dims = Dims(n_theta, n_atoms, n_voxels, n_fascicles, atom.shape[0])
+        self._h = ctypes.c_void_p()
+        flags = (PLAN_HOST_BUILD if host_build else 0) | (PLAN_DEVICE_INPUT if device_input else 0)
+        keep = []
+        if device_input:
+            keep = [torch.from_numpy(a).cuda() for a in (atom, voxel, fascicle, phi)]
+            ptrs = [ctypes.c_void_p(t.data_ptr()) if t.numel() else None for t in keep]
+            torch.cuda.synchronize()
+        else:
+            ptrs = [_np_ptr(a) for a in (atom, voxel, fascicle, phi)]
+        _check("life_plan_flags", load().life_plan_flags(ctypes.byref(self.dims), 1, None, None, *ptrs, _np_ptr(xyz),
+                                                         flags, ctypes.byref(self._h)))
+        del keep
+        self.device = torch.cuda.current_device()
+        return self
+
+    def digest(self) -> np.ndarray:
+        """Per-array hashes of the plan (life_plan_digest), to compare plans bit for bit."""
+        out = np.zeros(DIGEST_WORDS, np.uint64)
+        _check("life_plan_digest", load().life_plan_digest(self._h, _np_ptr(out)))
+        return out
 
     @classmethod
     def from_connectome(cls, c, morton: bool = True) -> "Plan":

@@ -199,3 +199,23 @@ def test_full_sbb_steps_teacher_forced(full, full_ref):
         assert s["iter"] == i + 1
         assert all(v <= TOL for v in errs.values()), (i, errs)
         w = ref.w.astype(np.float32)
+
+
+def test_full_device_plan_equals_host_plan(full):
+    """The plan the benchmark times (built on the device) equals, array for array,
+    the host builder's plan of the full connectome."""
+    import time
+    c, plan, dev = full
+    t0 = time.perf_counter()
+    host = life.Plan.build(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi,
+                           voxel_xyz=c.voxel_xyz, host_build=True)
+    t_host = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    again = life.Plan.from_connectome(c)
+    t_dev = time.perf_counter() - t0
+    print(f"[full] plan: device builder {t_dev:.3f} s, host builder {t_host:.3f} s", flush=True)
+    dh, dp = host.digest(), plan.digest()
+    assert np.array_equal(dp, dh), np.nonzero(dp != dh)[0]
+    assert np.array_equal(again.digest(), dh)
+    host.close()
+    again.close()
