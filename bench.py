@@ -274,6 +274,33 @@ def cpu_baseline(c, seq_seconds: float):
     return out
 
 
+def plan_build_times(c, morton: bool) -> dict:
+    """Restructuring times after the first build of the process (warm): from host
+    COO arrays (copied to the device inside the call), from COO arrays already on
+    the device, and the host builder once (the reference, only below 20M nonzeros)."""
+    import numpy as np
+    import torch
+    from paper_1905_06234_amd import life
+
+    xyz = c.voxel_xyz if morton else None
+    out = {}
+    args = (c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi)
+    t0 = time.perf_counter()
+    life.Plan.build(*args, voxel_xyz=xyz).close()
+    out["host_input"] = round((time.perf_counter() - t0) * 1e3, 1)
+    coo = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (c.atom, c.voxel, c.fascicle, c.phi)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    life.Plan.build(*args[:4], *coo, voxel_xyz=xyz).close()
+    out["device_input"] = round((time.perf_counter() - t0) * 1e3, 1)
+    del coo
+    if c.nnz < 20_000_000:
+        t0 = time.perf_counter()
+        life.Plan.build(*args, voxel_xyz=xyz, host_build=True).close()
+        out["host_builder"] = round((time.perf_counter() - t0) * 1e3, 1)
+    return out
+
+
 def _time_ms(fn, reps: int) -> float:
     """Wall milliseconds per call of fn (device-synchronized bracket)."""
     import torch
@@ -532,8 +559,10 @@ def main():
     t0 = time.perf_counter()
     plan = life.Plan.from_connectome(c, morton=args.voxel_order == "morton")
     plan_ms = (time.perf_counter() - t0) * 1e3
-    log(f"plan built in {plan_ms:.0f} ms")
+    log(f"plan built in {plan_ms:.0f} ms (first build of the process)")
     d = plan.dims
+    plan_times = plan_build_times(c, args.voxel_order == "morton")
+    log(f"plan builds: {plan_times}")
 
     D = torch.from_numpy(c.D.ravel()).to(dev)
     w = torch.from_numpy(c.w0).to(dev)
@@ -624,7 +653,7 @@ def main():
         if t_dsc + t_wc > 0 else None,
         "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},
         "kernel_launches": cnt,
-        "plan_ms": round(plan_ms, 1),
+        "plan_ms": round(plan_ms, 1), "plan_build_ms": plan_times,
         "roofline": roof,
     }
     if args.mall_flush:

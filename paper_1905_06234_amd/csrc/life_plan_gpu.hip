@@ -479,8 +479,10 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
                      const int32_t *fascicle, const float *phi, const int32_t *proc_pos_h, const int32_t *proc_vox,
                      int32_t n_pos, const int32_t *fas_inst_h, const int32_t *vox_off_h, int n_inst, DevLayout *out)
 {
-    DevLayout &L = *out;
-    L = DevLayout();
+    // built in L, handed to *out only on success: the arena frees L's arrays on
+    // every other return
+    *out = DevLayout();
+    DevLayout L;
     const int64_t n = d->nnz;
     const int nv = d->n_voxels, nf = d->n_fascicles, T = tg.n_tiles, TA = tg.tile_atoms;
     Arena ar;
@@ -583,12 +585,14 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
     if (!ok()) return fail();
     if (tg.row_floats == 0) {   // generic kernels: the canonical orders only
         L.n_chunks = 0;
+        e = hipDeviceSynchronize();
+        if (!ok()) return fail();
         for (void **p : {(void **)&L.vox_ptr, (void **)&L.fas_v, (void **)&L.fas_rank, (void **)&L.fas_ext,
                          (void **)&L.fas_ptr, (void **)&L.wc_perm, (void **)&L.vox_dsc, (void **)&L.atom_v,
                          (void **)&L.phi_v})
             ar.keep(*p);
-        e = hipDeviceSynchronize();
-        return ok() ? LIFE_OK : fail();
+        *out = L;
+        return LIFE_OK;
     }
 
     // ---- chunks: groups of kChunkVoxels positions, halved while they cross more than
@@ -628,9 +632,10 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
         }
         nb.push_back(bounds[(size_t)nc]);
         if (L.fas_overflow) {   // the caller falls back to the generic kernels
-            e = hipGetLastError();
-            if (ok()) e = hipDeviceSynchronize();
-            return ok() ? LIFE_OK : fail();
+            e = hipDeviceSynchronize();
+            if (!ok()) return fail();
+            out->fas_overflow = true;
+            return LIFE_OK;
         }
         if (!split) break;
         bounds.swap(nb);
@@ -759,6 +764,7 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
                      (void **)&L.rr_ptr, (void **)&L.rr, (void **)&L.atom_c, (void **)&L.loc_c, (void **)&L.wkey,
                      (void **)&L.phi_c, (void **)&L.wphi})
         ar.keep(*p);
+    *out = L;
     return LIFE_OK;
 }
 

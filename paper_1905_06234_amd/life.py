@@ -302,23 +302,35 @@ class Plan:
     def build(cls, n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle, phi,
               voxel_xyz=None, host_build: bool = False, device_input: bool = False) -> "Plan":
         """A single-problem plan through life_plan_flags.  host_build: restructure on
-        the host (the reference builder).  device_input: move atom, voxel, fascicle
-        and phi to the current device first and pass device pointers."""
+        the host (the reference builder).  atom, voxel, fascicle, phi: numpy arrays,
+        or device tensors (passed as device pointers); device_input with numpy
+        arrays moves them to the current device first."""
         torch = _torch()
         xyz = _xyz(voxel_xyz, n_voxels)
-        atom, voxel, fascicle = _coo(atom, voxel, fascicle)
-        phi = np.ascontiguousarray(phi, dtype=np.float32)
-        if phi.shape != atom.shape:
-            raise ValueError("phi must have one value per nonzero")
+        keep = []
+        if isinstance(atom, torch.Tensor):
+            # device tensors (int16, int32, int32, float32, contiguous, on the current device)
+            dt = (torch.int16, torch.int32, torch.int32, torch.float32)
+            keep = [atom, voxel, fascicle, phi]
+            n = atom.numel()
+            if not all(t.is_cuda and t.is_contiguous() and t.dtype == d and t.numel() == n for t, d in zip(keep, dt)):
+                raise ValueError("device COO tensors must be contiguous int16/int32/int32/float32 of one length")
+            device_input = True
+        else:
+            atom, voxel, fascicle = _coo(atom, voxel, fascicle)
+            phi = np.ascontiguousarray(phi, dtype=np.float32)
+            if phi.shape != atom.shape:
+                raise ValueError("phi must have one value per nonzero")
+            n = atom.shape[0]
+            if device_input:
+                keep = [torch.from_numpy(a).cuda() for a in (atom, voxel, fascicle, phi)]
+                torch.cuda.synchronize()
         self = cls.__new__(cls)
-        self.dims = Dims(n_theta, n_atoms, n_voxels, n_fascicles, atom.shape[0])
+        self.dims = Dims(n_theta, n_atoms, n_voxels, n_fascicles, n)
         self._h = ctypes.c_void_p()
         flags = (PLAN_HOST_BUILD if host_build else 0) | (PLAN_DEVICE_INPUT if device_input else 0)
-        keep = []
-        if device_input:
-            keep = [torch.from_numpy(a).cuda() for a in (atom, voxel, fascicle, phi)]
+        if keep:
             ptrs = [ctypes.c_void_p(t.data_ptr()) if t.numel() else None for t in keep]
-            torch.cuda.synchronize()
         else:
             ptrs = [_np_ptr(a) for a in (atom, voxel, fascicle, phi)]
         _check("life_plan_flags", load().life_plan_flags(ctypes.byref(self.dims), 1, None, None, *ptrs, _np_ptr(xyz),

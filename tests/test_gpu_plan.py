@@ -1,8 +1,8 @@
 """The device plan builder (the default of life_plan*) against the host builder
 (LIFE_PLAN_HOST_BUILD), bit for bit: every array of the plan is hashed
 (life_plan_digest) and the digests must be equal, for single problems (Morton and
-index order, duplicates, ragged and empty inputs, N_theta > 128), for
-device-resident inputs, and for
+index order, duplicates, ragged and empty inputs, N_theta > 128, a voxel that
+crosses more fascicles than a chunk holds), for device-resident inputs, and for
 batched plans; the canonical orders are also checked against numpy.lexsort."""
 import numpy as np
 import pytest
@@ -60,6 +60,34 @@ def test_device_builder_equals_host_builder(name, dev):
     assert relerr(_np(y), oracle.Operator.from_connectome(c).dsc(w)) <= 1e-5
     for p in (pg, ph, pd):
         p.close()
+
+
+def test_fascicle_overflow_falls_back(dev):
+    """One voxel crosses more distinct fascicles than a chunk holds: both builders
+    give the same generic plan, and its products stay right."""
+    rng = np.random.default_rng(9)
+    nf, nv = 17000, 20
+    heavy = np.arange(nf, dtype=np.int32)
+    rest = rng.integers(0, nf, 3000).astype(np.int32)
+    fas = np.concatenate([heavy, rest])
+    vox = np.concatenate([np.zeros(nf, np.int32), rng.integers(1, nv, 3000).astype(np.int32)])
+    atom = rng.integers(0, 60, fas.size).astype(np.int16)
+    phi = rng.uniform(0.3, 1.2, fas.size).astype(np.float32)
+    D = rng.standard_normal((60, 32)).astype(np.float32)
+    c = synth.Connectome(name="overflow", n_theta=32, n_atoms=60, n_voxels=nv, n_fascicles=nf, atom=atom, voxel=vox,
+                         fascicle=fas, phi=phi, D=D, w0=rng.random(nf).astype(np.float32),
+                         w_true=rng.random(nf).astype(np.float32),
+                         noise=rng.standard_normal(32 * nv).astype(np.float32), grid=None, voxel_xyz=None)
+    ph = _build(c, None, host_build=True)
+    op = oracle.Operator.from_connectome(c)
+    for label, p in (("host", ph), ("device", _build(c, None))):
+        print(f"[plan] overflow case, {label} builder", flush=True)
+        assert np.array_equal(p.digest(), ph.digest())
+        y = p.dsc(_t(c.D, dev), _t(c.w0, dev))
+        assert relerr(_np(y), op.dsc(c.w0)) <= 1e-5
+        g = p.wc(_t(c.D, dev), _t(c.noise, dev))
+        assert relerr(_np(g), op.wc(c.noise)) <= 1e-5
+    ph.close()
 
 
 def test_batched_device_builder_equals_host_builder(dev):
