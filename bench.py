@@ -35,7 +35,7 @@ os.environ.setdefault("OMP_PROC_BIND", "close")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # what the path computes in: float32 data and sums; the dense products inside WC
 # take FP16 hi/lo operand pairs on the matrix cores with FP32 accumulation
-ARITHMETIC = "f32; WC projections split-fp16 MFMA, fp32 accumulate"
+ARITHMETIC = "f32; WC projections exact int8-MFMA digit products of 30-bit fixed-point D and y, rounded once"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector; a plain v_fma_f32 loop reached 132 TFLOP/s here
 
 
@@ -439,10 +439,13 @@ def bench_batched(args):
     inst = synth.make_batch(args.instances, seed=7, scale=args.batch_scale)
     nnz = sum(c.nnz for c in inst)
     log(f"batched: {len(inst)} instances, nnz {nnz} ({time.perf_counter() - t0:.0f} s)")
-    bp = life.Plan.batch(inst)
-    singles = [life.Plan.from_connectome(c) for c in inst]
-    log("plans built")
     D = torch.from_numpy(inst[0].D.ravel()).to(dev)
+    t0 = time.perf_counter()
+    bp = life.Plan.autotune(inst, D, reps=3)
+    t_tune = time.perf_counter() - t0
+    singles = [life.Plan.from_connectome(c) for c in inst]
+    log(f"plans built; batched plan autotuned in {t_tune:.2f} s: {bp.tile_atoms} atoms per tile, "
+        f"schedule {bp.policy}")
     bs, ws = [], []
     for c, sp in zip(inst, singles):
         y = sp.dsc(D, torch.from_numpy(c.w_true).to(dev))
@@ -451,8 +454,7 @@ def bench_batched(args):
     b_all = torch.cat(bs)
     w_all = torch.cat(ws)
     states = life.new_state(dev, n=len(inst))
-    policy = bp.tune(D, w_all, b_all, reps=3)
-    log(f"tuned schedule {policy}")
+    policy = bp.policy
 
     def batched():
         bp.sbbnnls_step_batch(D, b_all, w_all, states)
@@ -483,7 +485,8 @@ def bench_batched(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_graph, 4), "ms_per_step_eager": round(t_batched, 4),
            "ms_per_step_sequential_plans": round(t_seq, 4), "speedup_vs_sequential": round(t_seq / t_graph, 3),
-           "schedule": policy, "dtype": "f32", "data": "synthetic",
+           "schedule": policy, "tile_atoms": bp.tile_atoms, "autotune_s": round(t_tune, 3),
+           "dtype": ARITHMETIC, "data": "synthetic",
            "config": {"workload": f"{len(inst)} uneven synthetic connectomes sharing D", "nnz": nnz,
                       "n_voxels": [c.n_voxels for c in inst], "n_fascicles": [c.n_fascicles for c in inst],
                       "scale": args.batch_scale}}
@@ -511,6 +514,8 @@ def main():
     ap.add_argument("--workload", default="sbb", choices=["sbb", "adam", "batched", "solve"],
                     help="sbb: the headline SBB-NNLS iteration; adam: dictionary learning steps on the mid "
                          "connectome; batched: uneven instances sharing D; solve: a whole SBB-NNLS solve")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sbb: time the plan geometry chosen by life_plan_autotune instead of the default one")
     ap.add_argument("--iterations", type=int, default=500, help="iterations of --workload solve")
     ap.add_argument("--adam-steps", type=int, default=200)
     ap.add_argument("--instances", type=int, default=32)
@@ -565,6 +570,14 @@ def main():
     log(f"plan builds: {plan_times}")
 
     D = torch.from_numpy(c.D.ravel()).to(dev)
+    tuned = None
+    if args.autotune:
+        plan.close()
+        t0 = time.perf_counter()
+        plan = life.Plan.autotune([c], D, reps=3, morton=args.voxel_order == "morton")
+        tuned = {"seconds": round(time.perf_counter() - t0, 3), "tile_atoms": plan.tile_atoms,
+                 "schedule": plan.policy}
+        log(f"autotuned plan: {tuned}")
     w = torch.from_numpy(c.w0).to(dev)
     # b = M w_true + 5% noise, formed with the library's own DSC (input preparation)
     y_true = plan.dsc(D, torch.from_numpy(c.w_true).to(dev))
@@ -653,9 +666,11 @@ def main():
         if t_dsc + t_wc > 0 else None,
         "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},
         "kernel_launches": cnt,
-        "plan_ms": round(plan_ms, 1), "plan_build_ms": plan_times,
+        "plan_ms": round(plan_ms, 1), "plan_build_ms": plan_times, "tile_atoms": plan.tile_atoms,
         "roofline": roof,
     }
+    if tuned:
+        out["autotune"] = tuned
     if args.mall_flush:
         out["cold_mall"] = cold_mall_kernels(plan, D, b, w, state, args.steps)
         log(f"cold-MALL kernel times: {out['cold_mall']}")

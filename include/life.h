@@ -169,11 +169,40 @@ enum {
  * which stays available as the reference.  With LIFE_PLAN_DEVICE_INPUT the COO
  * arrays are device memory of the current device (not retained; nothing is
  * copied from the host).  The host builder is also used when N_theta > 128 or a
- * voxel crosses more than 16384 fascicles.  Synchronous.
- * Errors: as life_plan_batch; LIFE_EINVAL for unknown flags. */
+ * voxel crosses more fascicles than a chunk holds (16384 at most).
+ * tile_atoms: 0 = the default dictionary tiling (as many atoms per LDS tile as
+ * 104 KB holds, then balanced), else at most that many atoms per tile (the
+ * tiles are balanced; fewer atoms per tile leave more LDS to the chunk's
+ * fascicle list; ignored when N_theta > 128).  Results are the same products for
+ * every tiling; summation orders differ.  Synchronous.
+ * Errors: as life_plan_batch; LIFE_EINVAL for unknown flags, tile_atoms < 0, or a
+ * tiling whose LDS blocks do not fit (checked before any device is touched). */
 life_status life_plan_flags(const life_dims *dims, int32_t n_inst, const int32_t *vox_off, const int32_t *fas_off,
                             const int16_t *atom, const int32_t *voxel, const int32_t *fascicle, const float *phi,
-                            const int16_t *voxel_xyz, uint32_t flags, life_plan_t *out);
+                            const int16_t *voxel_xyz, uint32_t flags, int32_t tile_atoms, life_plan_t *out);
+
+/* Atoms per dictionary tile of a plan (host output; 0 for the generic kernels
+ * used when N_theta > 128 or a chunk's fascicles overflow). */
+life_status life_plan_tile_atoms(life_plan_t plan, int32_t *tile_atoms);
+
+/* Choose the plan's geometry by measurement (the paper picks its kernel
+ * variants by timing runs on the input, Sec. 4.1), extended from the schedule
+ * to the dictionary tiling: a plan is built (as life_plan_flags, device
+ * builder) for each tiling of 3 to 8 balanced tiles that fits the LDS, each
+ * times reps DSC+WC pairs on D and fixed pseudo-random w and y, the fastest is
+ * kept and life_plan_tune then picks its schedule.  Every candidate computes
+ * the same products; only summation orders and speed differ.
+ *   flags: 0 or LIFE_PLAN_DEVICE_INPUT (as life_plan_flags).
+ *   D: device, the dictionary the plan will be used with (N_theta x N_a).
+ *   tile_atoms_out, policy_out (host, optional): the chosen tiling and schedule.
+ * Allocates two signals and two weight vectors of scratch for the timing;
+ * synchronizes the device.  Errors: as life_plan_flags; LIFE_EINVAL for
+ * reps < 1 or a missing D. */
+life_status life_plan_autotune(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                               const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                               const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz, uint32_t flags,
+                               const float *D, int32_t reps, int32_t *tile_atoms_out, int32_t *policy_out,
+                               life_plan_t *out);
 
 /* Digest of every array of a plan (one 64-bit FNV-1a hash per array, the last
  * word over the layout's sizes), to compare plans bit for bit.  digest: host,

@@ -13,8 +13,9 @@
 //
 // Two implementations of DSC and WC pass 1 exist:
 //   chunked (n_theta <= 128): a 1024-thread workgroup owns 64 voxels and works
-//     one atom tile at a time (a tile of D takes at most 80 KB: 5 tiles of 212
-//     atoms for N_theta = 96, so two DSC workgroups share a CU).
+//     one atom tile at a time (by default a tile of D takes at most 104 KB: 4
+//     tiles of 265 atoms for N_theta = 96; a plan may be built with other tile
+//     sizes, and life_plan_autotune picks one by timing).
 //     DSC stages the tile in LDS; inside a wave, four 16-lane groups each take one
 //     nonzero per step, lane l of a group holding theta = 32c + 2l, 2l + 1, so a
 //     step is 3 ds_read_b64 + 6 FMA per lane.  The per-nonzero scalars are loaded
@@ -1452,6 +1453,20 @@ extern "C" life_status life_plan(const life_dims *dims, const int16_t *atom, con
 
 namespace {
 
+// Whether the chunked kernels' LDS layouts fit a tiling: the WC pass-1 block
+// (the P tile of tile_atoms rows plus the chunk's Y digits), the dictionary
+// gradient's Psi block for a span of one tile, and the DSC tile beside a
+// fascicle list of at least 1024 weights (tile_geometry checks the last).
+bool tiling_fits(int n_theta, const life::TileGeom &tg)
+{
+    if (tg.row_floats == 0) return false;   // tile_geometry found no room for the DSC's fascicle list
+    const int ab = (tg.tile_atoms + 31) / 32, ks = (n_theta + 31) / 32;
+    const size_t wcr = (size_t)ab * 32 * kPS * sizeof(float) + (size_t)kDigits * kChunkVoxels * (32 * ks + kQ8Pad) +
+                       kChunkVoxels * sizeof(float);
+    const int64_t dd = (int64_t)((tg.tile_atoms + 15) / 16 * 16 + (n_theta + 15) / 16 * 16) * kPsiStride * 4;
+    return ab <= kChunkWaves && wcr <= (size_t)life::kLdsBudget && dd <= life::kLdsBudget;
+}
+
 // Plan construction shared by life_plan, life_plan_ex, life_plan_batch and
 // life_plan_flags (n_inst <= 1: a single problem).  The restructuring runs on the
 // device (life::plan_gpu) unless LIFE_PLAN_HOST_BUILD asks for the host builder,
@@ -1459,7 +1474,8 @@ namespace {
 // fascicles than a chunk holds; both builders give the same plan bit for bit.
 life_status build_plan(const life_dims *dims, const int16_t *atom_in, const int32_t *voxel_in,
                        const int32_t *fascicle_in, const float *phi_in, const int16_t *voxel_xyz, int n_inst,
-                       const int32_t *vox_off, const int32_t *fas_off, uint32_t flags, life_plan_t *out)
+                       const int32_t *vox_off, const int32_t *fas_off, uint32_t flags, int tile_atoms,
+                       life_plan_t *out)
 {
     if (!out) return LIFE_EINVAL;
     *out = nullptr;
@@ -1481,8 +1497,11 @@ life_status build_plan(const life_dims *dims, const int16_t *atom_in, const int3
         for (int k = 0; k < n_inst; ++k)
             if (vox_off[k + 1] < vox_off[k] || fas_off[k + 1] < fas_off[k]) return LIFE_EINVAL;
     }
-    const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms);
+    if (tile_atoms < 0) return LIFE_EINVAL;
+    const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms, tile_atoms);
     if (batched && tg.row_floats == 0) return LIFE_EINVAL;   // batched plans need N_theta <= 128
+    // an explicit tiling the chunked kernels cannot hold (ignored when N_theta > 128)
+    if (tile_atoms > 0 && d.n_theta <= life::kMaxTileRowFloats && !tiling_fits(d.n_theta, tg)) return LIFE_EINVAL;
     const int32_t n_pos = life::padded_positions(&d, n_inst, vox_off);
     if (n_pos < 0) return LIFE_ERANGE;
     int dev = 0;
@@ -1798,7 +1817,7 @@ extern "C" life_status life_plan_ex(const life_dims *dims, const int16_t *atom, 
                                     const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
                                     life_plan_t *out)
 {
-    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, 1, nullptr, nullptr, 0, out);
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, 1, nullptr, nullptr, 0, 0, out);
 }
 
 extern "C" life_status life_plan_batch(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
@@ -1807,17 +1826,157 @@ extern "C" life_status life_plan_batch(const life_dims *dims, int32_t n_inst, co
                                        life_plan_t *out)
 {
     if (n_inst < 1 || !vox_off || !fas_off) return LIFE_EINVAL;
-    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, 0, out);
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, 0, 0, out);
 }
 
 extern "C" life_status life_plan_flags(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
                                        const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
                                        const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
-                                       uint32_t flags, life_plan_t *out)
+                                       uint32_t flags, int32_t tile_atoms, life_plan_t *out)
 {
     if (n_inst < 1 || (n_inst > 1 && (!vox_off || !fas_off))) return LIFE_EINVAL;
     if (flags & ~(uint32_t)(LIFE_PLAN_DEVICE_INPUT | LIFE_PLAN_HOST_BUILD)) return LIFE_EINVAL;
-    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, flags, out);
+    return build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, flags, tile_atoms,
+                      out);
+}
+
+extern "C" life_status life_plan_tile_atoms(life_plan_t plan, int32_t *tile_atoms)
+{
+    if (!plan || !tile_atoms) return LIFE_EINVAL;
+    *tile_atoms = chunked(plan) ? plan->tile.tile_atoms : 0;
+    return LIFE_OK;
+}
+
+namespace {
+
+// x[i] = a deterministic pseudo-random value in [lo, lo + span) (inputs of the timing runs)
+__global__ void k_fill_hash(float *x, int64_t n, uint32_t seed, float lo, float span)
+{
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    h *= 3266489917u;
+    h ^= h >> 16;
+    x[i] = lo + span * (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+// Milliseconds of reps DSC + WC pairs of a plan on (D, w, y) (one warm-up pair first).
+life_status time_pairs(life_plan_s *p, const float *D, const float *w, const float *y, float *yo, float *go, int reps,
+                       float *ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LIFE_EDEVICE;
+    life_status st = LIFE_OK;
+    for (int i = -1; i < reps && st == LIFE_OK; ++i) {
+        if (i == 0 && hipEventRecord(e0, nullptr) != hipSuccess) st = LIFE_EDEVICE;
+        if (st == LIFE_OK) st = life_dsc(p, D, w, yo, nullptr);
+        if (st == LIFE_OK) st = life_wc(p, D, y, go, nullptr);
+    }
+    if (st == LIFE_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+        st = LIFE_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" life_status life_plan_autotune(const life_dims *dims, int32_t n_inst, const int32_t *vox_off,
+                                          const int32_t *fas_off, const int16_t *atom, const int32_t *voxel,
+                                          const int32_t *fascicle, const float *phi, const int16_t *voxel_xyz,
+                                          uint32_t flags, const float *D, int32_t reps, int32_t *tile_atoms_out,
+                                          int32_t *policy_out, life_plan_t *out)
+{
+    if (!out || !dims || reps < 1 || (dims->n_theta > 0 && dims->n_atoms > 0 && !D)) return LIFE_EINVAL;
+    *out = nullptr;
+    if (flags & ~(uint32_t)LIFE_PLAN_DEVICE_INPUT) return LIFE_EINVAL;
+    life_status st = life::validate_dims(dims);
+    if (st != LIFE_OK) return st;
+    const life_dims d = *dims;
+    // candidate tiles: 3, 4, 5, 6 and 8 tiles of the dictionary (those the LDS holds)
+    std::vector<int> cands;
+    for (int nt : {5, 4, 6, 3, 8}) {
+        const int ta = (d.n_atoms + nt - 1) / nt;
+        const life::TileGeom tg = life::tile_geometry(d.n_theta, d.n_atoms, ta);
+        if (tiling_fits(d.n_theta, tg) && std::find(cands.begin(), cands.end(), tg.tile_atoms) == cands.end())
+            cands.push_back(tg.tile_atoms);
+    }
+    if (cands.empty()) {   // N_theta > 128: one (generic) plan, nothing to choose
+        st = build_plan(dims, atom, voxel, fascicle, phi, voxel_xyz, n_inst, vox_off, fas_off, flags, 0, out);
+        if (st == LIFE_OK && tile_atoms_out) *tile_atoms_out = 0;
+        if (st == LIFE_OK && policy_out) *policy_out = (*out)->schedule;
+        return st;
+    }
+    // the COO arrays on the device once; every candidate is built from them
+    void *coo[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *buf[4] = {nullptr, nullptr, nullptr, nullptr};   // w, y, y out, g out
+    life_plan_t best = nullptr;
+    float best_ms = 0.f;
+    int best_ta = 0;
+    st = LIFE_OK;
+    auto cleanup = [&]() {
+        for (void *q : coo)
+            if (q) (void)hipFree(q);
+        for (float *q : buf)
+            if (q) (void)hipFree(q);
+    };
+    const int16_t *a_d = atom;
+    const int32_t *v_d = voxel, *f_d = fascicle;
+    const float *p_d = phi;
+    if (!(flags & LIFE_PLAN_DEVICE_INPUT) && d.nnz > 0) {
+        const size_t sz[4] = {sizeof(int16_t), sizeof(int32_t), sizeof(int32_t), sizeof(float)};
+        const void *src[4] = {atom, voxel, fascicle, phi};
+        for (int i = 0; i < 4 && st == LIFE_OK; ++i) {
+            if (!src[i] || hipMalloc(&coo[i], sz[i] * (size_t)d.nnz) != hipSuccess ||
+                hipMemcpy(coo[i], src[i], sz[i] * (size_t)d.nnz, hipMemcpyHostToDevice) != hipSuccess)
+                st = src[i] ? LIFE_EDEVICE : LIFE_EINVAL;
+        }
+        a_d = static_cast<const int16_t *>(coo[0]);
+        v_d = static_cast<const int32_t *>(coo[1]);
+        f_d = static_cast<const int32_t *>(coo[2]);
+        p_d = static_cast<const float *>(coo[3]);
+    }
+    const int64_t nsig = (int64_t)d.n_theta * d.n_voxels, nw = d.n_fascicles;
+    const int64_t lens[4] = {nw, nsig, nsig, nw};
+    for (int i = 0; i < 4 && st == LIFE_OK; ++i)
+        if (lens[i] > 0 && hipMalloc(&buf[i], sizeof(float) * (size_t)lens[i]) != hipSuccess) st = LIFE_ENOMEM;
+    if (st == LIFE_OK && nw > 0) k_fill_hash<<<cdiv(nw, kBlock), kBlock>>>(buf[0], nw, 12345u, 0.f, 1.f);
+    if (st == LIFE_OK && nsig > 0) k_fill_hash<<<cdiv(nsig, kBlock), kBlock>>>(buf[1], nsig, 777u, -1.f, 2.f);
+    for (size_t k = 0; k < cands.size() && st == LIFE_OK; ++k) {
+        life_plan_t p = nullptr;
+        st = build_plan(dims, a_d, v_d, f_d, p_d, voxel_xyz, n_inst, vox_off, fas_off, LIFE_PLAN_DEVICE_INPUT,
+                        cands[k], &p);
+        if (st != LIFE_OK) break;
+        float ms = 0.f;
+        st = time_pairs(p, D, buf[0], buf[1], buf[2], buf[3], reps, &ms);
+        if (st != LIFE_OK) {
+            (void)life_plan_destroy(p);
+            break;
+        }
+        if (!best || ms < best_ms) {
+            if (best) (void)life_plan_destroy(best);
+            best = p;
+            best_ms = ms;
+            best_ta = cands[k];
+        } else {
+            (void)life_plan_destroy(p);
+        }
+    }
+    int32_t pol = 0;
+    if (st == LIFE_OK && best) st = life_plan_tune(best, D, buf[0], buf[1], reps, &pol);
+    cleanup();
+    if (st != LIFE_OK) {
+        if (best) (void)life_plan_destroy(best);
+        return st;
+    }
+    *out = best;
+    if (tile_atoms_out) *tile_atoms_out = chunked(best) ? best_ta : 0;
+    if (policy_out) *policy_out = pol;
+    return LIFE_OK;
 }
 
 namespace {

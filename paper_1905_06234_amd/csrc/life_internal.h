@@ -54,9 +54,11 @@ constexpr int kWaveVoxels = 4;
 constexpr int kChunkVoxels = kChunkWaves * kWaveVoxels;
 constexpr int kMaxTileRowFloats = 128;      // chunked kernels handle n_theta <= 128
 constexpr int kLdsBudget = 160 * 1024 - 1024;
-// A staged dictionary tile takes at most half of a CU's LDS, so that two DSC
-// workgroups (64 VGPRs per lane: 8 waves per SIMD) share a CU.
-constexpr int kTileBytes = 80 * 1024;
+// Default size of a staged dictionary tile (4 tiles of 265 atoms at N_theta = 96:
+// fewer restagings of D per chunk than 80 KB tiles, measured 4% faster per SBB
+// step on the full connectome); a plan may ask for other tile sizes
+// (life_plan_flags, life_plan_autotune).
+constexpr int kTileBytes = 104 * 1024;
 // Dictionary-gradient kernel: per tile, a dense (atom x voxel slot) block of the
 // chunk and the chunk's (theta x voxel slot) signal block in LDS, rows of
 // kPsiStride floats (64 slots + 4 to spread the banks); a tile has at most
@@ -68,9 +70,13 @@ struct TileGeom {
     int row_floats = 0;   // LDS row length (floats), 0 = chunked kernels not applicable
     int tile_atoms = 0;
     int n_tiles = 0;
+    int fas_cap = 0;      // distinct fascicles a chunk may cross (DSC keeps their weights in LDS beside a tile)
 };
 
-TileGeom tile_geometry(int n_theta, int n_atoms);
+// Tiles of at most tile_atoms atoms (0: as many as kTileBytes holds), balanced;
+// row_floats = 0 when N_theta > 128 or the requested tile leaves no LDS for the
+// chunk's weights.
+TileGeom tile_geometry(int n_theta, int n_atoms, int tile_atoms = 0);
 
 // Chunks.  Processing positions are cut into groups of kChunkVoxels consecutive
 // positions (instance blocks of batched plans are whole groups, so no group spans
@@ -82,7 +88,7 @@ TileGeom tile_geometry(int n_theta, int n_atoms);
 // generic kernels.  A chunk is one workgroup of kChunkWaves waves; each wave owns
 // up to kWaveVoxels voxel slots, balanced inside the chunk by longest-processing-
 // time assignment (ties keep processing order).
-constexpr int kChunkFasCap = 16384;
+constexpr int kChunkFasCap = 16384;   // at most (kChunkFasCap is also the 16-bit local index's bound)
 constexpr uint16_t kRunStart = 0x8000;
 
 // Chunked layout: for every (chunk c, tile t, wave w) one contiguous range of the

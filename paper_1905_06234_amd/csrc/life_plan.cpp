@@ -242,16 +242,21 @@ life_status plan_host(const life_dims *d, const int16_t *atom, const int32_t *vo
     return LIFE_OK;
 }
 
-TileGeom tile_geometry(int n_theta, int n_atoms)
+TileGeom tile_geometry(int n_theta, int n_atoms, int tile_atoms)
 {
     TileGeom g;
     const int row = ((n_theta + 31) / 32) * 32;
     if (row > kMaxTileRowFloats) return g;
-    const int max_atoms = std::min(kTileBytes / (row * 4), kMaxTileAtoms);
+    const int max_atoms = std::min(tile_atoms > 0 ? tile_atoms : kTileBytes / (row * 4), kMaxTileAtoms);
     const int n_tiles = (n_atoms + max_atoms - 1) / max_atoms;
+    const int ta = (n_atoms + n_tiles - 1) / n_tiles;   // balanced tiles
+    // the LDS left beside one tile holds the chunk's weights (at least 1024 of them)
+    const int cap = std::min(kChunkFasCap, (kLdsBudget - ta * row * 4) / 4);
+    if (cap < 1024) return g;
     g.row_floats = row;
     g.n_tiles = n_tiles;
-    g.tile_atoms = (n_atoms + n_tiles - 1) / n_tiles;   // balanced tiles
+    g.tile_atoms = ta;
+    g.fas_cap = cap;
     return g;
 }
 
@@ -342,13 +347,13 @@ life_status chunk_layout(const life_dims *d, const TileGeom &tg, const int32_t *
             const auto r = todo.back();
             todo.pop_back();
             const int n = distinct_fascicles(vox_ptr, fas_v, proc_vox, r.first, r.second, stamp, tag++);
-            if (n > kChunkFasCap && r.second - r.first > 1) {
+            if (n > tg.fas_cap && r.second - r.first > 1) {
                 const int32_t mid = r.first + (r.second - r.first) / 2;
                 todo.push_back({mid, r.second});   // LIFO: the lower half is cut first
                 todo.push_back({r.first, mid});
                 continue;
             }
-            if (n > kChunkFasCap) L.fas_overflow = true;
+            if (n > tg.fas_cap) L.fas_overflow = true;
             L.bounds.push_back(r.second);
         }
     }

@@ -596,7 +596,7 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
     }
 
     // ---- chunks: groups of kChunkVoxels positions, halved while they cross more than
-    // kChunkFasCap distinct fascicles (counted as distinct (rank, chunk) pairs of the
+    // tg.fas_cap distinct fascicles (counted as distinct (rank, chunk) pairs of the
     // WC order, where they are adjacent)
     std::vector<int32_t> bounds;
     for (int32_t g0 = 0; g0 < n_pos; g0 += kChunkVoxels) bounds.push_back(g0);
@@ -621,7 +621,7 @@ life_status plan_gpu(const life_dims *d, const TileGeom &tg, const int16_t *atom
         bool split = false;
         for (int c = 0; c < nc; ++c) {
             nb.push_back(bounds[c]);
-            if (cnt_h[(size_t)c] > kChunkFasCap) {
+            if (cnt_h[(size_t)c] > tg.fas_cap) {
                 if (bounds[c + 1] - bounds[c] > 1) {
                     nb.push_back(bounds[c] + (bounds[c + 1] - bounds[c]) / 2);
                     split = true;

@@ -56,7 +56,11 @@ _SIGS = {
                                        ctypes.POINTER(_P)]),
     "life_plan_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "life_plan_flags": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
-                                       ctypes.c_uint32, ctypes.POINTER(_P)]),
+                                       ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "life_plan_tile_atoms": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "life_plan_autotune": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                          ctypes.c_uint32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)]),
     "life_plan_digest": (ctypes.c_int, [_P, _P]),
     "life_plan_host_batch": (ctypes.c_int, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
                                             _P, _P, _P, _P]),
@@ -262,7 +266,7 @@ class Plan:
         if host_build:
             _check("life_plan_flags", load().life_plan_flags(
                 ctypes.byref(self.dims), n_inst, _np_ptr(vox_off), _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
-                _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz), PLAN_HOST_BUILD, ctypes.byref(self._h)))
+                _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz), PLAN_HOST_BUILD, 0, ctypes.byref(self._h)))
         else:
             _check("life_plan_batch", load().life_plan_batch(ctypes.byref(self.dims), n_inst, _np_ptr(vox_off),
                                                              _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
@@ -299,12 +303,40 @@ class Plan:
         return w
 
     @classmethod
+    def autotune(cls, instances, D, reps: int = 3, morton: bool = True) -> "Plan":
+        """The fastest plan geometry for these problems (life_plan_autotune): one
+        instance gives a single-problem plan, several a batched plan.  The chosen
+        tiling and schedule are in ``tile_atoms`` and ``policy``."""
+        dims, vox_off, fas_off, atom, voxel, fascicle, phi, xyz = concat_instances(instances, morton)
+        n_inst = len(vox_off) - 1
+        self = cls.__new__(cls)
+        self.dims = dims
+        self._h = ctypes.c_void_p()
+        ta, pol = ctypes.c_int32(), ctypes.c_int32()
+        _check("life_plan_autotune", load().life_plan_autotune(
+            ctypes.byref(self.dims), n_inst, _np_ptr(vox_off), _np_ptr(fas_off), _np_ptr(atom), _np_ptr(voxel),
+            _np_ptr(fascicle), _np_ptr(phi), _np_ptr(xyz), 0, self._d(D), int(reps), ctypes.byref(ta),
+            ctypes.byref(pol), ctypes.byref(self._h)))
+        self.device = _torch().cuda.current_device()
+        self.vox_off, self.fas_off = vox_off, fas_off
+        self.policy = int(pol.value)
+        return self
+
+    @property
+    def tile_atoms(self) -> int:
+        """Atoms per dictionary tile (0: generic kernels)."""
+        n = ctypes.c_int32()
+        _check("life_plan_tile_atoms", load().life_plan_tile_atoms(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    @classmethod
     def build(cls, n_theta: int, n_atoms: int, n_voxels: int, n_fascicles: int, atom, voxel, fascicle, phi,
-              voxel_xyz=None, host_build: bool = False, device_input: bool = False) -> "Plan":
+              voxel_xyz=None, host_build: bool = False, device_input: bool = False, tile_atoms: int = 0) -> "Plan":
         """A single-problem plan through life_plan_flags.  host_build: restructure on
         the host (the reference builder).  atom, voxel, fascicle, phi: numpy arrays,
         or device tensors (passed as device pointers); device_input with numpy
-        arrays moves them to the current device first."""
+        arrays moves them to the current device first.  tile_atoms: at most that
+        many atoms per dictionary tile (0: the default tiling)."""
         torch = _torch()
         xyz = _xyz(voxel_xyz, n_voxels)
         keep = []
@@ -334,7 +366,7 @@ class Plan:
         else:
             ptrs = [_np_ptr(a) for a in (atom, voxel, fascicle, phi)]
         _check("life_plan_flags", load().life_plan_flags(ctypes.byref(self.dims), 1, None, None, *ptrs, _np_ptr(xyz),
-                                                         flags, ctypes.byref(self._h)))
+                                                         flags, int(tile_atoms), ctypes.byref(self._h)))
         del keep
         self.device = torch.cuda.current_device()
         return self

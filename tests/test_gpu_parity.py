@@ -30,12 +30,12 @@ RANDOM_SHAPES = {
     "r96big": (96, 1057, 4000, 3000, 200_000, False),
     "empty": (16, 64, 512, 200, 0, False),
     "sparsevox": (64, 20, 20_000, 50, 700, False),
-    # one chunk, one atom tile, more nonzeros than WC pass 1's LDS stage holds
-    # (~19k values at N_theta = 96, ~5k at 16), so part of z bypasses the stage
+    # one chunk, one atom tile, hundreds of nonzeros per voxel: long runs of one
+    # (atom, voxel) pair in the WC buckets and a chunk fascicle list of thousands
     "dense96": (96, 200, 64, 5000, 30_000, True),
     "dense16": (16, 512, 64, 3000, 20_000, False),
-    # one chunk over 5 atom tiles with twice the stage's capacity: the overflow part of
-    # z is grouped by tile
+    # one chunk over 4 atom tiles, thousands of fascicles: a long WC bucket per
+    # (chunk, tile) and a fascicle list near the chunk's LDS capacity
     "dense96t": (96, 1057, 64, 8000, 40_000, False),
 }
 

@@ -223,6 +223,18 @@ def test_batch_plan_needs_chunked_geometry():
     assert e.value.status == 1
 
 
+def test_explicit_tiling_checked_before_the_device():
+    """life_plan_flags rejects a tiling whose LDS blocks do not fit at N_theta = 96
+    (one tile of 500 atoms: the WC pass-1 block alone needs 160,000 bytes), and a
+    negative tile_atoms, before any device is touched."""
+    c = synth.random_coo(96, 500, 64, 100, 2000, seed=3)
+    for ta in (500, -1):
+        with pytest.raises(life.LifeError) as e:
+            life.Plan.build(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.atom, c.voxel, c.fascicle, c.phi,
+                            tile_atoms=ta)
+        assert e.value.status == 1, ta
+
+
 def test_batch_ranks_with_empty_instances():
     """Instances without voxels (leading and in the middle) and instances whose
     fascicles are all empty: every instance's ranks are exactly its own block
