@@ -65,7 +65,7 @@ def profile_commands(config: str) -> dict:
 
 
 PROFILE_COMMANDS = profile_commands("full")
-KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcz_mfma", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
+KIND_KERNELS = {"dsc": ("k_dsc_chunk", "k_dsc"), "wc_z": ("k_wcr_mfma", "k_wc_z"), "wc_sum": ("k_wc_sum",)}
 # profiling classes launched by the same kernel (the second WC of even iterations)
 KIND_GROUPS = {"dsc": ("dsc",), "wc_z": ("wc_z", "wc_z_2nd"), "wc_sum": ("wc_sum", "wc_sum_2nd")}
 
