@@ -600,7 +600,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = life.read_state(state)
-    log(f"timed {args.steps} steps: {wall * 1e3:.2f} ms; f={st['obj']:.6e} alpha={st['alpha']:.3e}")
+    w_zero = float((w == 0).float().mean().item())
+    log(f"timed {args.steps} steps: {wall * 1e3:.2f} ms; f={st['obj']:.6e} alpha={st['alpha']:.3e}; "
+        f"zero weights {w_zero:.3f}")
     # per-kernel times from a separate pass of K steps with every launch bracketed by events
     plan.profile_read()                 # drop anything recorded so far
     plan.profile_enable(True)
@@ -638,6 +640,16 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(bw / HBM_PEAK_GBS, 4)}
+    # DSC alone at growing fractions of zero weights (the zero-weight skip, Sec. 6.6)
+    rng = np.random.default_rng(11)
+    y_buf = torch.empty(d.n_theta * d.n_voxels, dtype=torch.float32, device=dev)
+    dsc_zero = {}
+    for frac in (0.0, 0.5, 0.9, 0.99):
+        wz = torch.from_numpy(np.where(rng.random(d.n_fascicles) < frac, 0.0, c.w0).astype(np.float32)).to(dev)
+        plan.dsc(D, wz, y_buf)
+        dsc_zero[str(frac)] = round(_time_ms(lambda: plan.dsc(D, wz, y_buf), 10), 4)
+    del y_buf
+    log(f"DSC ms by fraction of zero weights: {dsc_zero}")
     # achievable stream bandwidth on this GPU: a plain 1 GiB device copy (read + write)
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -666,6 +678,7 @@ def main():
         if t_dsc + t_wc > 0 else None,
         "kernel_avg_ms": {k: round(v, 4) for k, v in avg.items()},
         "kernel_launches": cnt,
+        "w_zero_fraction_after_timed_steps": round(w_zero, 4), "dsc_ms_by_zero_fraction": dsc_zero,
         "plan_ms": round(plan_ms, 1), "plan_build_ms": plan_times, "tile_atoms": plan.tile_atoms,
         "roofline": roof,
     }

@@ -226,10 +226,29 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float *wl = lds + TA * ROW;
+    __shared__ int zero_w[kChunkWaves];   // zero weights among the chunk's fascicles, per wave
+    const int f0 = cfas_ptr[chunk], nl = cfas_ptr[chunk + 1] - f0;
     {
-        const int f0 = cfas_ptr[chunk], nl = cfas_ptr[chunk + 1] - f0;
-        for (int i = threadIdx.x; i < nl; i += kWG) wl[i] = w[cfas[f0 + i]];
-    }   // visible after the first barrier of the tile loop
+        int nz = 0;
+        for (int i = threadIdx.x; i < nl; i += kWG) {
+            const float wv = w[cfas[f0 + i]];
+            wl[i] = wv;
+            nz += wv == 0.f;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) nz += __shfl_xor(nz, o, 64);
+        if (lane == 0) zero_w[wave] = nz;
+    }
+    // the first tile (its LDS region is not the weights')
+    stage_tile<ROW>(lds, D, 0, min(na, TA), nth, vec);
+    __syncthreads();
+    // zero-weight skip (Sec. 2.2) where at least 1/8 of the chunk's weights are zero:
+    // a batch without a nonzero product then costs nothing, and one with few moves
+    // them to its first steps; denser chunks run the plain loop (no per-batch test)
+    int n_zero = 0;
+#pragma unroll
+    for (int i = 0; i < kChunkWaves; ++i) n_zero += zero_w[i];
+    const bool skip = uni(8 * n_zero >= nl ? 1 : 0) != 0;
     const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
@@ -238,69 +257,104 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
 #pragma unroll
         for (int e = 0; e < PER; ++e) acc[j][e] = 0.f;
 
-    for (int t = 0; t < T; ++t) {
-        const int a0 = t * TA;
-        __syncthreads();
-        stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
-        const WaveRange R(wave_work, chunk, t, T, wave);
-        __syncthreads();
-        if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
-        // two-stage prefetch over batch starts: the scalars of batch i+2 and the
-        // w gather of batch i+1 are in flight while batch i is computed
-        int bq = R.next(R.p[0]);
-        int ix = R.entry(R.p[0], mypos);
-        int a_0 = atom[ix], f_0 = loc[ix];
-        float ph_0 = phi[ix];
-        ix = R.entry(bq, mypos);
-        int a_1 = atom[ix], f_1 = loc[ix];
-        float ph_1 = phi[ix];
-        float w_0 = wl[f_0];
+    auto tiles = [&](auto skip_tag) {
+        constexpr bool SKIP = decltype(skip_tag)::value;
+        for (int t = 0; t < T; ++t) {
+            const int a0 = t * TA;
+            if (t > 0) {   // (tile 0 is staged above)
+                __syncthreads();
+                stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
+                __syncthreads();
+            }
+            const WaveRange R(wave_work, chunk, t, T, wave);
+            if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
+            // two-stage prefetch over batch starts: the scalars of batch i+2 and the
+            // w gather of batch i+1 are in flight while batch i is computed
+            int bq = R.next(R.p[0]);
+            int ix = R.entry(R.p[0], mypos);
+            int a_0 = atom[ix], f_0 = loc[ix];
+            float ph_0 = phi[ix];
+            ix = R.entry(bq, mypos);
+            int a_1 = atom[ix], f_1 = loc[ix];
+            float ph_1 = phi[ix];
+            float w_0 = wl[f_0];
 #pragma unroll
-        for (int j = 0; j < kWaveVoxels; ++j) {
-            for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
-                const int m = min(kBatch, R.p[j + 1] - b);
-                const int a_c = a_0;
-                const float ph_c = ph_0, w_c = w_0;
-                const float w_1 = wl[f_1];
-                bq = R.next(bq);
-                ix = R.entry(bq, mypos);
-                a_0 = a_1;
-                ph_0 = ph_1;
-                w_0 = w_1;
-                a_1 = atom[ix];
-                f_1 = loc[ix];
-                ph_1 = phi[ix];
-                const bool valid = mypos < m;
-                const int aoff = valid ? (a_c - a0) * ROW : 0;
-                const float s = valid ? ph_c * w_c : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
+            for (int j = 0; j < kWaveVoxels; ++j) {
+                for (int b = R.p[j]; b < R.p[j + 1]; b += kBatch) {
+                    const int m = min(kBatch, R.p[j + 1] - b);
+                    const int a_c = a_0;
+                    const float ph_c = ph_0, w_c = w_0;
+                    const float w_1 = wl[f_1];
+                    bq = R.next(bq);
+                    ix = R.entry(bq, mypos);
+                    a_0 = a_1;
+                    ph_0 = ph_1;
+                    w_0 = w_1;
+                    a_1 = atom[ix];
+                    f_1 = loc[ix];
+                    ph_1 = phi[ix];
+                    const bool valid = mypos < m;
+                    int aoff = valid ? (a_c - a0) * ROW : 0;
+                    float s = valid ? ph_c * w_c : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
+                    // (SKIP: a batch without a nonzero product costs nothing; one with few
+                    // nonzero products moves them to its first steps)
 #define LIFE_DSC_STEP(K)                                                                  \
-    {                                                                                     \
-        const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
-        const float sk = bcast16f<K>(s);                                                  \
-        _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
-            const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
-            acc[j][2 * cc + 0] = fmaf(d.x, sk, acc[j][2 * cc + 0]);                       \
-            acc[j][2 * cc + 1] = fmaf(d.y, sk, acc[j][2 * cc + 1]);                       \
-        }                                                                                 \
-    }
-                if (m == kBatch) {
-                    LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
-                    LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
-                    LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11)
-                    LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15)
-                } else {
-                    const int ns = m / kSE;     // sub-ranges are padded to whole steps
+        {                                                                                     \
+            const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
+            const float sk = bcast16f<K>(s);                                                  \
+            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
+                const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
+                acc[j][2 * cc + 0] = fmaf(d.x, sk, acc[j][2 * cc + 0]);                       \
+                acc[j][2 * cc + 1] = fmaf(d.y, sk, acc[j][2 * cc + 1]);                       \
+            }                                                                                 \
+        }
+                    int n = m;   // entries to cover (the rest carry zero products)
+                    if constexpr (SKIP) {
+                        const uint64_t nzm = __ballot(s != 0.f);
+                        const int cnt = __popcll(nzm);
+                        if (cnt == 0) n = 0;
+                        else if ((cnt + 15) / 16 < (m + 15) / 16) {
+                        // compaction, when it saves steps: the r-th nonzero product (in lane
+                        // order) goes to position r = kSE k + g of the batch (step k, group g),
+                        // the zero products after them; every lane sends one value, so every
+                        // lane receives one (a permutation of the wave)
+                        const uint64_t below = (1ull << lane) - 1;
+                        const int r = s != 0.f ? __popcll(nzm & below) : cnt + __popcll(~nzm & below);
+                        const int dst = kGL * (r % kSE) + r / kSE;
+                        aoff = __builtin_amdgcn_ds_permute(4 * dst, aoff);
+                        s = __int_as_float(__builtin_amdgcn_ds_permute(4 * dst, __float_as_int(s)));
+                        n = cnt;
+                        }
+                    }
+                    if (n == kBatch) {
+                        LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
+                        LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7)
+                        LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11)
+                        LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15)
+                    } else if (SKIP && n > 0) {
+                        // blocks of four steps (16 entries); entries past n have zero products
+                        LIFE_DSC_STEP(0) LIFE_DSC_STEP(1) LIFE_DSC_STEP(2) LIFE_DSC_STEP(3)
+                        if (n > 16) { LIFE_DSC_STEP(4) LIFE_DSC_STEP(5) LIFE_DSC_STEP(6) LIFE_DSC_STEP(7) }
+                        if (n > 32) { LIFE_DSC_STEP(8) LIFE_DSC_STEP(9) LIFE_DSC_STEP(10) LIFE_DSC_STEP(11) }
+                        if (n > 48) { LIFE_DSC_STEP(12) LIFE_DSC_STEP(13) LIFE_DSC_STEP(14) LIFE_DSC_STEP(15) }
+                    } else if (!SKIP) {
+                        const int ns = m / kSE;     // sub-ranges are padded to whole steps
 #define LIFE_DSC_GSTEP(K) if (K < ns) LIFE_DSC_STEP(K)
-                    LIFE_DSC_GSTEP(0) LIFE_DSC_GSTEP(1) LIFE_DSC_GSTEP(2) LIFE_DSC_GSTEP(3)
-                    LIFE_DSC_GSTEP(4) LIFE_DSC_GSTEP(5) LIFE_DSC_GSTEP(6) LIFE_DSC_GSTEP(7)
-                    LIFE_DSC_GSTEP(8) LIFE_DSC_GSTEP(9) LIFE_DSC_GSTEP(10) LIFE_DSC_GSTEP(11)
-                    LIFE_DSC_GSTEP(12) LIFE_DSC_GSTEP(13) LIFE_DSC_GSTEP(14)
+                        LIFE_DSC_GSTEP(0) LIFE_DSC_GSTEP(1) LIFE_DSC_GSTEP(2) LIFE_DSC_GSTEP(3)
+                        LIFE_DSC_GSTEP(4) LIFE_DSC_GSTEP(5) LIFE_DSC_GSTEP(6) LIFE_DSC_GSTEP(7)
+                        LIFE_DSC_GSTEP(8) LIFE_DSC_GSTEP(9) LIFE_DSC_GSTEP(10) LIFE_DSC_GSTEP(11)
+                        LIFE_DSC_GSTEP(12) LIFE_DSC_GSTEP(13) LIFE_DSC_GSTEP(14)
 #undef LIFE_DSC_GSTEP
-                }
+                    }
 #undef LIFE_DSC_STEP
+                }
             }
         }
-    }
+    };
+    if (skip)
+        tiles(std::true_type{});
+    else
+        tiles(std::false_type{});
 
     // combine the group partials (fixed butterfly) and write each column once
     double sq = 0.0;

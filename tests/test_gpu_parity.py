@@ -98,6 +98,34 @@ def test_dsc_parity(name, dev):
         assert relerr(_np(y), ref) <= TOL, (name, label)
 
 
+@pytest.mark.parametrize("name", ["tiny", "mid", "r5dup", "r100", "r96big", "dense96", "dense16", "sparsevox"])
+def test_dsc_zero_weight_skip(name, dev):
+    """DSC with mostly-zero weights (the zero-weight skip compacts each batch's
+    nonzero products): random 90% and 99% zeros, a contiguous half of the
+    fascicles zero, negative zeros, and all zeros (y must then be exactly 0)."""
+    c, op, plan = problem(name, dev)
+    D = _t(c.D, dev)
+    rng = np.random.default_rng(17)
+    nf = c.n_fascicles
+    pats = {
+        "90%": np.where(rng.random(nf) < 0.9, 0.0, c.w0),
+        "99%": np.where(rng.random(nf) < 0.99, 0.0, c.w0),
+        "half": np.where(np.arange(nf) < nf // 2, 0.0, c.w0),
+        "-0": np.where(rng.random(nf) < 0.7, -0.0, c.w0),
+    }
+    for label, w in pats.items():
+        w = np.asarray(w, np.float32)
+        y = plan.dsc(D, _t(w, dev))
+        ref = op.dsc(w)
+        if np.abs(ref).max() == 0:
+            assert np.all(_np(y) == 0), (name, label)
+        else:
+            assert relerr(_np(y), ref) <= TOL, (name, label)
+        assert torch.equal(plan.dsc(D, _t(w, dev)), y), (name, label)   # bitwise repeatable
+    y0 = plan.dsc(D, torch.zeros(nf, device=dev))
+    assert torch.count_nonzero(y0).item() == 0
+
+
 @pytest.mark.parametrize("name", ALL)
 def test_wc_parity(name, dev):
     c, op, plan = problem(name, dev)
