@@ -41,6 +41,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector; a plain v_fma_f32 loop re
 
 # rocprofv3 commands whose outputs --summarize reads (run from /tmp with
 # TMPDIR=/tmp; the synthetic connectome cached through LIFE_SYNTH_CACHE)
+# SQ counters, two passes (at most 8 SQ counters per run)
+SQ_PASS1 = ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU",
+            "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_MISC")
+SQ_PASS2 = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_SALU",
+            "SQ_LDS_IDX_ACTIVE", "SQ_WAVES", "SQ_INSTS_MFMA")
+
+
 def profile_commands(config: str) -> dict:
     """The rocprofv3 runs behind profiles/<config>_*: a kernel trace, then FETCH_SIZE,
     WRITE_SIZE and the L2 hit counters in runs of their own, and the copy probe that
@@ -48,15 +55,15 @@ def profile_commands(config: str) -> dict:
     cfg = "" if config == "full" else f" --config {config}"
     out = "$R/gpurun_out/prof" + ("" if config == "full" else f"_{config}")
     run = f"python3 $R/bench.py{cfg}"
+    short = f"{run} --steps 2 --warmup 1 --no-cpu-baseline --no-extras"
     return {
         "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/trace -o run -- "
-                 f"{run} --steps 6 --warmup 2 --no-cpu-baseline",
-        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/fetch -o run -- "
-                 f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
-        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/write -o run -- "
-                 f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
-        "tcc": f"rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d {out}/tcc -o run -- "
-               f"{run} --steps 2 --warmup 1 --no-cpu-baseline",
+                 f"{run} --steps 6 --warmup 2 --no-cpu-baseline --no-extras",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/fetch -o run -- {short}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/write -o run -- {short}",
+        "tcc": f"rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d {out}/tcc -o run -- {short}",
+        "sq1": f"rocprofv3 --pmc {' '.join(SQ_PASS1)} --output-format csv -d {out}/sq1 -o run -- {short}",
+        "sq2": f"rocprofv3 --pmc {' '.join(SQ_PASS2)} --output-format csv -d {out}/sq2 -o run -- {short}",
         "copyf": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/copyf -o run -- "
                  "python3 $R/bench.py --copy-probe",
         "copyw": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/copyw -o run -- "
@@ -156,9 +163,43 @@ def summarize(prof_dir: str, workload: str):
               "`LIFE_SYNTH_CACHE=/tmp/life_synth`), then "
               f"`python3 bench.py{'' if workload == 'full' else ' --config ' + workload} --summarize "
               f"$R/gpurun_out/prof{'' if workload == 'full' else '_' + workload}`:", ""]
-    lines += [f"    {c}" for c in profile_commands(workload).values()]
+    lines += [f"    {c}" for k, c in profile_commands(workload).items() if not k.startswith("sq")]
     with open(os.path.join(out_dir, f"{workload}_kernels.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    sq = {}
+    for d in ("sq1", "sq2"):
+        sq.update(_counter_means(os.path.join(prof_dir, d)))
+    if sq:
+        names = sorted({k for (k, c) in sq if k.startswith("k_")})
+        cols = [c for c in SQ_PASS1 + SQ_PASS2 if any((n, c) in sq for n in names)]
+        frac = {"SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_MISC"}
+        sl = [f"# SQ counters, {workload} synthetic connectome", "",
+              "Per-dispatch means. Columns marked `/wave` are divided by `SQ_WAVE_CYCLES` (the share of",
+              "wave-cycles spent waiting or issuing); `LDS_BANK_CONFLICT` is also given as a share of",
+              "`SQ_LDS_IDX_ACTIVE`. Taken on the library sources of the same SHA-256 as",
+              f"`{workload}_kernels.md`.", "",
+              "| kernel | " + " | ".join(c.replace("SQ_", "") + (" /wave" if c in frac else "") for c in cols)
+              + " | bank conflict share |",
+              "|---" * (len(cols) + 2) + "|"]
+        for n in names:
+            wc = sq.get((n, "SQ_WAVE_CYCLES"), (0, 0.0))[1]
+            row = []
+            for c in cols:
+                v = sq.get((n, c))
+                if v is None:
+                    row.append("-")
+                elif c in frac and wc > 0:
+                    row.append(f"{v[1] / wc:.3f}")
+                else:
+                    row.append(f"{v[1]:.3g}")
+            bc, act = sq.get((n, "SQ_LDS_BANK_CONFLICT")), sq.get((n, "SQ_LDS_IDX_ACTIVE"))
+            share = f"{bc[1] / act[1]:.3f}" if bc and act and act[1] > 0 else "-"
+            sl.append(f"| `{n}` | " + " | ".join(row) + f" | {share} |")
+        sl += ["", "Commands (as for the kernel table):", ""]
+        sl += [f"    {profile_commands(workload)[k]}" for k in ("sq1", "sq2")]
+        with open(os.path.join(out_dir, f"{workload}_sq_counters.md"), "w") as fh:
+            fh.write("\n".join(sl) + "\n")
     print(json.dumps({"summarized": workload, "kernels": list(kernels)}))
 
 
@@ -505,6 +546,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target time of the one-core sequential oracle sample (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plan-builder timings and the DSC timings at sparse weights (profiler runs)")
     ap.add_argument("--voxel-order", default="morton", choices=["morton", "index"],
                     help="voxel processing order of the plan: Morton order of the grid coordinates, or voxel index")
     ap.add_argument("--mall-flush", action="store_true",
@@ -566,7 +609,7 @@ def main():
     plan_ms = (time.perf_counter() - t0) * 1e3
     log(f"plan built in {plan_ms:.0f} ms (first build of the process)")
     d = plan.dims
-    plan_times = plan_build_times(c, args.voxel_order == "morton")
+    plan_times = None if args.no_extras else plan_build_times(c, args.voxel_order == "morton")
     log(f"plan builds: {plan_times}")
 
     D = torch.from_numpy(c.D.ravel()).to(dev)
@@ -644,7 +687,7 @@ def main():
     rng = np.random.default_rng(11)
     y_buf = torch.empty(d.n_theta * d.n_voxels, dtype=torch.float32, device=dev)
     dsc_zero = {}
-    for frac in (0.0, 0.5, 0.9, 0.99):
+    for frac in () if args.no_extras else (0.0, 0.5, 0.9, 0.99):
         wz = torch.from_numpy(np.where(rng.random(d.n_fascicles) < frac, 0.0, c.w0).astype(np.float32)).to(dev)
         plan.dsc(D, wz, y_buf)
         dsc_zero[str(frac)] = round(_time_ms(lambda: plan.dsc(D, wz, y_buf), 10), 4)

@@ -70,10 +70,16 @@ def test_summary_scales_counters_by_the_copy_probe(tmp_path, monkeypatch):
 def test_profile_commands_per_config():
     b = _bench()
     full, mid = b.profile_commands("full"), b.profile_commands("mid")
-    assert full == b.PROFILE_COMMANDS and set(full) == {"trace", "fetch", "write", "tcc", "copyf", "copyw"}
+    assert full == b.PROFILE_COMMANDS
+    assert set(full) == {"trace", "fetch", "write", "tcc", "sq1", "sq2", "copyf", "copyw"}
+    # each SQ pass stays within the 8 SQ counters one run can collect
+    for k in ("sq1", "sq2"):
+        pmc = full[k].split("--pmc ")[1].split(" --")[0].split()
+        assert 0 < len(pmc) <= 8 and all(c.startswith("SQ_") for c in pmc)
+        assert "--kernel-trace" not in full[k] and "--sys-trace" not in full[k]
     assert "--config" not in full["trace"] and "gpurun_out/prof/" in full["trace"]
     assert all("gpurun_out/prof_mid/" in c for c in mid.values())
-    assert all("--config mid" in mid[k] for k in ("trace", "fetch", "write", "tcc"))
+    assert all("--config mid" in mid[k] for k in ("trace", "fetch", "write", "tcc", "sq1", "sq2"))
     # counters never share a run with the trace, and one counter block per run
     assert all("--pmc" not in full[k] for k in ("trace",)) and "--kernel-trace" not in full["fetch"]
 
