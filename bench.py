@@ -394,7 +394,7 @@ def bench_solve(args):
     print(json.dumps({
         "metric": "SBB-NNLS solve: wall time per iteration (2 DSC + 1 or 2 WC + glue, all on the device)",
         "value": round(elapsed * 1e3 / args.iterations, 4), "unit": "ms/iteration", "higher_is_better": False,
-        "n_gpus": 1, "iterations": args.iterations, "total_s": round(elapsed, 4), "dtype": "f32",
+        "n_gpus": 1, "iterations": args.iterations, "total_s": round(elapsed, 4), "dtype": ARITHMETIC,
         "data": "synthetic", "config": {"workload": f"{args.config} synthetic connectome", "nnz": c.nnz,
                                         "voxel_order": args.voxel_order},
         "objective": {"at_w0": trace[0][1], "last": trace[-1][1], "trace": trace},
@@ -456,7 +456,7 @@ def bench_adam(args):
     out = {"metric": "joint (w, D) Adam step on ||y_obs - M(D)w||^2 / plain DSC+WC pair time",
            "value": round(t_adam / t_pair, 4), "unit": "ratio", "higher_is_better": False, "n_gpus": 1,
            "steps": args.adam_steps, "warmup": args.warmup, "ms_per_adam_step": round(t_adam, 4),
-           "ms_per_dsc_wc_pair": round(t_pair, 4), "dtype": "f32", "data": "synthetic",
+           "ms_per_dsc_wc_pair": round(t_pair, 4), "dtype": ARITHMETIC, "data": "synthetic",
            "loss_before": L0, "loss_after": L1, "kernel_avg_ms": avg,
            "config": {"workload": "mid synthetic connectome, dictionary learning", "n_theta": c.n_theta,
                       "n_atoms": c.n_atoms, "n_voxels": c.n_voxels, "n_fascicles": c.n_fascicles, "nnz": c.nnz}}
@@ -521,11 +521,29 @@ def bench_batched(args):
     with torch.cuda.graph(graph):
         batched()
     t_graph = _time_ms(graph.replay, args.steps)
+
+    # time inside the library's launches (events around each launch group), per step
+    def kernel_ms(plans, fn):
+        for p in plans:
+            p.profile_read()
+            p.profile_enable(True)
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        tot = 0.0
+        for p in plans:
+            p.profile_enable(False)
+            tot += sum(p.profile_read()[0].values())
+        return tot / args.steps
+    k_batched = kernel_ms([bp], batched)
+    k_seq = kernel_ms(singles, sequential)
+    log(f"kernel time per step: batched {k_batched:.3f} ms, sequential plans {k_seq:.3f} ms")
     out = {"metric": "Phi nonzeros/s for one batched SBB-NNLS iteration over all instances (hipGraph replay)",
            "value": round(nnz * 3.5 / 2 / (t_graph / 1e3), 1), "unit": "nnz/s", "higher_is_better": True,
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_graph, 4), "ms_per_step_eager": round(t_batched, 4),
            "ms_per_step_sequential_plans": round(t_seq, 4), "speedup_vs_sequential": round(t_seq / t_graph, 3),
+           "kernel_ms_per_step_batched": round(k_batched, 4), "kernel_ms_per_step_sequential": round(k_seq, 4),
            "schedule": policy, "tile_atoms": bp.tile_atoms, "autotune_s": round(t_tune, 3),
            "dtype": ARITHMETIC, "data": "synthetic",
            "config": {"workload": f"{len(inst)} uneven synthetic connectomes sharing D", "nnz": nnz,
