@@ -476,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
 // Per tile, waves 0..AB-1 first form P = D_tile^T Y_chunk in LDS (one 32-atom block
 // each, both 32-slot halves); then every wave walks its own entry range of the
 // (chunk, tile) bucket (cut at run starts) in batches of 64 consecutive entries,
-// the next batch in flight: each lane looks up its entry's projection in P, and a
+// four batches requested at once: each lane looks up its entry's projection in P, and a
 // segmented scan over the batch (Hillis-Steele with run-start flags, fixed order)
 // sums each run; the lane at a run's end writes it, a run that crosses into the
 // next batch carries its partial sum there.
@@ -576,36 +576,47 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
         if (eb >= ee) continue;
         int run = uni(wc_wrun[wi]);      // index of the run open before the current batch, plus one
         float carry = 0.f;
-        int kn = eb + lane < ee ? (int)wkey[eb + lane] : (int)life::kRunStart;
-        float pn = eb + lane < ee ? wphi[eb + lane] : 0.f;
-        for (int b = eb; b < ee; b += 64) {
-            const int key = kn;
-            const float ph = pn;
-            const int e2 = b + 64 + lane;
-            kn = e2 < ee ? (int)wkey[e2] : (int)life::kRunStart;
-            pn = e2 < ee ? wphi[e2] : 0.f;
-            const bool in = b + lane < ee;
-            const bool st = (key & life::kRunStart) != 0;
-            float v = in ? ph * P[((key >> 6) & 0x1ff) * kPS + (key & 63)] : 0.f;
-            if (lane == 0 && !st) v += carry;
-            // inclusive segmented scan (a run start stops the sums from the left)
-            int f = st ? 1 : 0;
+        for (int b0 = eb; b0 < ee; b0 += 4 * 64) {
+            // four batches of keys and values requested at once, and the key after them
+            int kk[4];
+            float pp[4];
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const float vu = __shfl_up(v, d, 64);
-                const int fu = __shfl_up(f, d, 64);
-                if (lane >= d && !f) {
-                    v += vu;
-                    f |= fu;
-                }
+            for (int u = 0; u < 4; ++u) {
+                const int e = b0 + 64 * u + lane;
+                kk[u] = e < ee ? (int)wkey[e] : (int)life::kRunStart;
+                pp[u] = e < ee ? wphi[e] : 0.f;
             }
-            const uint64_t starts = __ballot(st);
-            const int next_key0 = __shfl(kn, 0, 64);   // the entry after this batch (a start past the range)
-            const bool nxt = lane < 63 ? ((starts >> (lane + 1)) & 1) != 0 : (next_key0 & life::kRunStart) != 0;
-            const int before = __popcll(starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
-            if (in && nxt) zrun[run + before - 1] = v;
-            run += __popcll(starts & __ballot(in));
-            carry = __shfl(v, 63, 64);   // used only if the next batch does not start a run
+            const int after = b0 + 256 < ee ? (int)wkey[b0 + 256] : (int)life::kRunStart;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + 64 * u;
+                if (b >= ee) break;   // uniform
+                const int key = kk[u];
+                const float ph = pp[u];
+                const bool in = b + lane < ee;
+                const bool st = (key & life::kRunStart) != 0;
+                float v = in ? ph * P[((key >> 6) & 0x1ff) * kPS + (key & 63)] : 0.f;
+                if (lane == 0 && !st) v += carry;
+                // inclusive segmented scan (a run start stops the sums from the left)
+                int f = st ? 1 : 0;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const float vu = __shfl_up(v, d, 64);
+                    const int fu = __shfl_up(f, d, 64);
+                    if (lane >= d && !f) {
+                        v += vu;
+                        f |= fu;
+                    }
+                }
+                const uint64_t starts = __ballot(st);
+                // the entry after this batch (a start past the range)
+                const int next_key0 = u < 3 ? __shfl(kk[u < 3 ? u + 1 : 3], 0, 64) : after;
+                const bool nxt = lane < 63 ? ((starts >> (lane + 1)) & 1) != 0 : (next_key0 & life::kRunStart) != 0;
+                const int before = __popcll(starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1)));
+                if (in && nxt) zrun[run + before - 1] = v;
+                run += __popcll(starts & __ballot(in));
+                carry = __shfl(v, 63, 64);   // used only if the next batch does not start a run
+            }
         }
     }
 }
@@ -812,10 +823,25 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
     for (int c = c0; c < c1; ++c) {
         __syncthreads();                          // the previous chunk's products are done with the LDS
         for (int i = threadIdx.x; i < n4; i += kWG) lds4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int i = threadIdx.x; i < kChunkVoxels * NT16; i += kWG) {
-            const int slot = i / NT16, th = i - slot * NT16;
-            const int v = chunk_vox[(size_t)c * kChunkVoxels + slot];
-            ylds[th * kPsiStride + slot] = (v >= 0 && th < nth) ? ybar[(size_t)v * nth + th] : 0.f;
+        // the chunk's ybar block (at most 64 x 128 values: 8 per thread, 4 in flight)
+        for (int i0 = threadIdx.x; i0 < kChunkVoxels * NT16; i0 += 4 * kWG) {
+            int vv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * kWG;
+                vv[k] = i < kChunkVoxels * NT16 ? chunk_vox[(size_t)c * kChunkVoxels + i / NT16] : -1;
+            }
+            float yv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int th = (i0 + k * kWG) % NT16;
+                yv[k] = (vv[k] >= 0 && th < nth) ? ybar[(size_t)vv[k] * nth + th] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k * kWG, slot = i / NT16, th = i - slot * NT16;
+                if (i < kChunkVoxels * NT16) ylds[th * kPsiStride + slot] = yv[k];
+            }
         }
         __syncthreads();
         // Psi of this chunk and dd tile: one nonzero per lane, four batches of 64 in
