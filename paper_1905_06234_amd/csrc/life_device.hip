@@ -207,9 +207,7 @@ template <int NC>
 __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ chunk_map,
                                                    const int32_t *__restrict__ chunk_vox,
                                                    const int32_t *__restrict__ wave_work,
-                                                   const int16_t *__restrict__ atom,
-                                                   const uint16_t *__restrict__ loc,
-                                                   const float *__restrict__ phi,
+                                                   const uint2 *__restrict__ rec,
                                                    const int32_t *__restrict__ cfas_ptr,
                                                    const int32_t *__restrict__ cfas,
                                                    const float *__restrict__ w,
@@ -272,11 +270,13 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
             // w gather of batch i+1 are in flight while batch i is computed
             int bq = R.next(R.p[0]);
             int ix = R.entry(R.p[0], mypos);
-            int a_0 = atom[ix], f_0 = loc[ix];
-            float ph_0 = phi[ix];
+            uint2 r = rec[ix];
+            int a_0 = (int)(r.x & 0xffffu), f_0 = (int)(r.x >> 16);
+            float ph_0 = __uint_as_float(r.y);
             ix = R.entry(bq, mypos);
-            int a_1 = atom[ix], f_1 = loc[ix];
-            float ph_1 = phi[ix];
+            r = rec[ix];
+            int a_1 = (int)(r.x & 0xffffu), f_1 = (int)(r.x >> 16);
+            float ph_1 = __uint_as_float(r.y);
             float w_0 = wl[f_0];
 #pragma unroll
             for (int j = 0; j < kWaveVoxels; ++j) {
@@ -290,9 +290,10 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
                     a_0 = a_1;
                     ph_0 = ph_1;
                     w_0 = w_1;
-                    a_1 = atom[ix];
-                    f_1 = loc[ix];
-                    ph_1 = phi[ix];
+                    r = rec[ix];
+                    a_1 = (int)(r.x & 0xffffu);
+                    f_1 = (int)(r.x >> 16);
+                    ph_1 = __uint_as_float(r.y);
                     const bool valid = mypos < m;
                     int aoff = valid ? (a_c - a0) * ROW : 0;
                     float s = valid ? ph_c * w_c : 0.f;   // loop-invariant product hoisted (Sec. 4.1)
@@ -1147,6 +1148,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ w, 
 
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// rec[i] = (atom | local index << 16, bits of phi): the chunked DSC stream in one record
+__global__ __launch_bounds__(kBlock) void k_pack_dsc(const int16_t *__restrict__ atom, const uint16_t *__restrict__ loc,
+                                                      const float *__restrict__ phi, int64_t n, uint2 *__restrict__ rec)
+{
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i < n) rec[i] = make_uint2((uint32_t)(uint16_t)atom[i] | (uint32_t)loc[i] << 16, __float_as_uint(phi[i]));
+}
+
 }  // namespace
 
 // ============================================================================= plan object
@@ -1192,6 +1201,7 @@ struct life_plan_s {
     int32_t *fas_c = nullptr;     // [n_pad] fascicle rank
     uint16_t *loc_c = nullptr;    // [n_pad] place of the fascicle in its chunk's list
     float *phi_c = nullptr;       // [n_pad]
+    uint2 *dsc_rec = nullptr;     // [n_pad] the DSC stream packed: (atom | local index << 16, phi)
     int32_t *cfas_ptr = nullptr;  // [n_chunks + 1] chunk fascicle lists (see life::ChunkLayout)
     int32_t *cfas = nullptr;
     int max_fas = 0;              // longest chunk fascicle list
@@ -1261,6 +1271,7 @@ hipError_t dalloc(T **p, int64_t n)
 void free_plan(life_plan_s *p)
 {
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c,
+                    p->dsc_rec,
                     p->fas_c, p->loc_c, p->phi_c, p->cfas_ptr, p->cfas, p->wkey, p->wphi, p->wc_wave, p->wc_wrun,
                     p->rr_ptr, p->rr, p->fas_rank, p->fas_ext, p->fas_ptr,
                     p->wc_perm, p->ws_base, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
@@ -1432,8 +1443,8 @@ life_status enqueue_dsc(life_plan_s *p, const float *D, const float *w, const fl
         const int nc = p->tile.row_floats / 32;
         return launch(p, LIFE_K_DSC, s, [&] {
             LIFE_DISPATCH_NC(nc, k_dsc_chunk, p->chunk_grid, kWG, p->dsc_lds, s>>>(p->chunk_map, p->chunk_vox,
-                                                                                  p->wave_work, p->atom_c, p->loc_c,
-                                                                                  p->phi_c, p->cfas_ptr, p->cfas, w, D,
+                                                                                  p->wave_work, p->dsc_rec,
+                                                                                  p->cfas_ptr, p->cfas, w, D,
                                                                                   bsub, y, part, nth,
                                                                                   p->dims.n_atoms, p->tile.n_tiles,
                                                                                   p->tile.tile_atoms, vec_tile(p, D)))
@@ -1856,6 +1867,12 @@ life_status build_plan(const life_dims *dims, const int16_t *atom_in, const int3
     take(&p->wc_wrun, G.wc_wrun, L.wc_wrun);
     take(&p->rr_ptr, G.rr_ptr, L.rr_ptr);
     take(&p->rr, G.rr, L.rr);
+    if (n_chunks > 0) {
+        // the DSC reads its stream as one 8-byte record per entry
+        chk(dalloc(&p->dsc_rec, n_pad));
+        if (e == hipSuccess && n_pad > 0)
+            k_pack_dsc<<<cdiv(n_pad, kBlock), kBlock>>>(p->atom_c, p->loc_c, p->phi_c, n_pad, p->dsc_rec);
+    }
     chk(dalloc(&p->chunk_map, (int64_t)cmap.size()));
     up(p->chunk_map, cmap.data(), sizeof(int32_t) * cmap.size());
     {
