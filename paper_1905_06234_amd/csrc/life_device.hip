@@ -485,8 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
 // conflict-free 16-byte reads along theta), the 64 slot scales.
 __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ chunk_map,
                                                   const int32_t *__restrict__ chunk_vox,
-                                                  const uint16_t *__restrict__ wkey,
-                                                  const float *__restrict__ wphi,
+                                                  const uint2 *__restrict__ wrec,
                                                   const int32_t *__restrict__ wc_wave,
                                                   const int32_t *__restrict__ wc_wrun,
                                                   const i32x4 *__restrict__ frag,
@@ -584,10 +583,11 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = b0 + 64 * u + lane;
-                kk[u] = e < ee ? (int)wkey[e] : (int)life::kRunStart;
-                pp[u] = e < ee ? wphi[e] : 0.f;
+                const uint2 r = wrec[e < ee ? e : ee - 1];
+                kk[u] = e < ee ? (int)r.x : (int)life::kRunStart;
+                pp[u] = e < ee ? __uint_as_float(r.y) : 0.f;
             }
-            const int after = b0 + 256 < ee ? (int)wkey[b0 + 256] : (int)life::kRunStart;
+            const int after = b0 + 256 < ee ? (int)wrec[b0 + 256].x : (int)life::kRunStart;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int b = b0 + 64 * u;
@@ -1148,6 +1148,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ w, 
 
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// rec[i] = (key, bits of phi): the WC pass-1 bucket stream in one record
+__global__ __launch_bounds__(kBlock) void k_pack_wc(const uint16_t *__restrict__ key, const float *__restrict__ phi,
+                                                     int64_t n, uint2 *__restrict__ rec)
+{
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i < n) rec[i] = make_uint2((uint32_t)key[i], __float_as_uint(phi[i]));
+}
+
 // rec[i] = (atom | local index << 16, bits of phi): the chunked DSC stream in one record
 __global__ __launch_bounds__(kBlock) void k_pack_dsc(const int16_t *__restrict__ atom, const uint16_t *__restrict__ loc,
                                                       const float *__restrict__ phi, int64_t n, uint2 *__restrict__ rec)
@@ -1209,6 +1217,7 @@ struct life_plan_s {
     // WC pass 1 buckets (see life::ChunkLayout) and pass 2 run lists
     uint16_t *wkey = nullptr;     // [nnz]
     float *wphi = nullptr;        // [nnz]
+    uint2 *wc_rec = nullptr;      // [nnz] (wkey, bits of wphi): WC pass 1 reads one record per entry
     int32_t *wc_wave = nullptr;   // [n_chunks * n_tiles * kChunkWaves + 1]
     int32_t *wc_wrun = nullptr;   // [n_chunks * n_tiles * kChunkWaves]
     int64_t n_runs = 0;
@@ -1273,6 +1282,7 @@ void free_plan(life_plan_s *p)
     void *ptrs[] = {p->vox_ptr, p->atom_v, p->fas_v, p->phi_v, p->chunk_vox, p->chunk_map, p->wave_work, p->atom_c,
                     p->dsc_rec,
                     p->fas_c, p->loc_c, p->phi_c, p->cfas_ptr, p->cfas, p->wkey, p->wphi, p->wc_wave, p->wc_wrun,
+                    p->wc_rec,
                     p->rr_ptr, p->rr, p->fas_rank, p->fas_ext, p->fas_ptr,
                     p->wc_perm, p->ws_base, p->a_ptr, p->a_vox, p->a_fas, p->a_phi, p->inst_chunk, p->inst_rank};
     for (void *q : ptrs)
@@ -1472,7 +1482,7 @@ life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, cons
                     k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, ws.dt_frag, ws.dt_scale,
                                                                                          nth, p->dims.n_atoms, T, TA,
                                                                                          AB, KS, gate);
-                k_wcr_mfma<<<p->chunk_grid, kWG, p->wcr_lds, s>>>(p->chunk_map, p->chunk_vox, p->wkey, p->wphi,
+                k_wcr_mfma<<<p->chunk_grid, kWG, p->wcr_lds, s>>>(p->chunk_map, p->chunk_vox, p->wc_rec,
                                                                   p->wc_wave, p->wc_wrun, ws.dt_frag, ws.dt_scale, y,
                                                                   ws.z, nth, T, AB, KS, gate);
             });
@@ -1872,6 +1882,9 @@ life_status build_plan(const life_dims *dims, const int16_t *atom_in, const int3
         chk(dalloc(&p->dsc_rec, n_pad));
         if (e == hipSuccess && n_pad > 0)
             k_pack_dsc<<<cdiv(n_pad, kBlock), kBlock>>>(p->atom_c, p->loc_c, p->phi_c, n_pad, p->dsc_rec);
+        chk(dalloc(&p->wc_rec, d.nnz));
+        if (e == hipSuccess && d.nnz > 0)
+            k_pack_wc<<<cdiv(d.nnz, kBlock), kBlock>>>(p->wkey, p->wphi, d.nnz, p->wc_rec);
     }
     chk(dalloc(&p->chunk_map, (int64_t)cmap.size()));
     up(p->chunk_map, cmap.data(), sizeof(int32_t) * cmap.size());
