@@ -2003,6 +2003,7 @@ extern "C" life_status life_plan_autotune(const life_dims *dims, int32_t n_inst,
 {
     if (!out || !dims || reps < 1 || (dims->n_theta > 0 && dims->n_atoms > 0 && !D)) return LIFE_EINVAL;
     *out = nullptr;
+    if (n_inst < 1 || (n_inst > 1 && (!vox_off || !fas_off))) return LIFE_EINVAL;
     if (flags & ~(uint32_t)LIFE_PLAN_DEVICE_INPUT) return LIFE_EINVAL;
     life_status st = life::validate_dims(dims);
     if (st != LIFE_OK) return st;

@@ -235,6 +235,24 @@ def test_explicit_tiling_checked_before_the_device():
         assert e.value.status == 1, ta
 
 
+def test_autotune_arguments_checked_before_the_device():
+    """life_plan_autotune rejects missing offsets of a batched plan, reps < 1, a
+    missing dictionary and unknown flags with LIFE_EINVAL before touching a device."""
+    lib = life.load()
+    c = synth.random_coo(16, 8, 40, 10, 200, seed=4)
+    dims = life.Dims(c.n_theta, c.n_atoms, c.n_voxels, c.n_fascicles, c.nnz)
+    arrs = [np.ascontiguousarray(a) for a in (c.atom, c.voxel, c.fascicle, c.phi)]
+    ptrs = [life._np_ptr(a) for a in arrs]
+    D = ctypes.c_void_p(16)   # never dereferenced: every case fails its argument checks first
+    out = ctypes.c_void_p()
+    ta, pol = ctypes.c_int32(), ctypes.c_int32()
+    for n_inst, d, reps, flags in ((2, D, 1, 0), (1, D, 0, 0), (1, None, 1, 0), (1, D, 1, 2), (0, D, 1, 0)):
+        st = lib.life_plan_autotune(ctypes.byref(dims), n_inst, None, None, *ptrs, None, flags, d, reps,
+                                    ctypes.byref(ta), ctypes.byref(pol), ctypes.byref(out))
+        assert st == 1, (n_inst, d, reps, flags)
+        assert not out.value
+
+
 def test_batch_ranks_with_empty_instances():
     """Instances without voxels (leading and in the middle) and instances whose
     fascicles are all empty: every instance's ranks are exactly its own block
