@@ -150,6 +150,20 @@ __device__ __forceinline__ float dppf(float x)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
+// One step of a wave-wide inclusive segmented scan of (v, f) (f: a segment starts
+// in the lane's range) on DPP moves: the partial from the lane CTRL selects (row
+// shift or row broadcast; lanes without a source, or outside ROW_MASK, get the
+// neutral (0, 0)) is added unless a segment starts in the lane's own range.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(float &v, int &f)
+{
+    const float vu = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+    const int fu = __builtin_amdgcn_update_dpp(0, f, CTRL, ROW_MASK, 0xf, true);
+    if (!f) {
+        v += vu;
+        f |= fu;
+    }
+}
 // broadcast lane K of every row to the row (row_newbcast)
 template <int K>
 __device__ __forceinline__ int bcast16(int x)
@@ -600,15 +614,12 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
                 if (lane == 0 && !st) v += carry;
                 // inclusive segmented scan (a run start stops the sums from the left)
                 int f = st ? 1 : 0;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const float vu = __shfl_up(v, d, 64);
-                    const int fu = __shfl_up(f, d, 64);
-                    if (lane >= d && !f) {
-                        v += vu;
-                        f |= fu;
-                    }
-                }
+                seg_scan_step<0x111, 0xf>(v, f);   // row_shr:1, 2, 4, 8 inside 16-lane rows
+                seg_scan_step<0x112, 0xf>(v, f);
+                seg_scan_step<0x114, 0xf>(v, f);
+                seg_scan_step<0x118, 0xf>(v, f);
+                seg_scan_step<0x142, 0xa>(v, f);   // row_bcast:15 into rows 1 and 3
+                seg_scan_step<0x143, 0xc>(v, f);   // row_bcast:31 into rows 2 and 3
                 const uint64_t starts = __ballot(st);
                 // the entry after this batch (a start past the range)
                 const int next_key0 = u < 3 ? __shfl(kk[u < 3 ? u + 1 : 3], 0, 64) : after;
