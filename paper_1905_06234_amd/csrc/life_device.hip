@@ -884,15 +884,19 @@ __global__ __launch_bounds__(kWG) void k_dd_chunk(const int32_t *__restrict__ ch
                         const int j = (idx >= p1) + (idx >= p2) + (idx >= p3);
                         const int key = valid ? (j << 16) | aa[h] : -1;
                         float v = valid ? sv[h] : 0.f;
-#pragma unroll
-                        for (int o = 1; o < 64; o <<= 1) {
-                            const float vo = __shfl_up(v, o, 64);
-                            const int ko = __shfl_up(key, o, 64);
-                            if (lane >= o && ko == key) v += vo;
-                        }
-                        const int kn = __shfl_down(key, 1, 64);
-                        if (valid && (lane == 63 || kn != key))
-                            psi[(aa[h] - a0) * kPsiStride + wave * kWaveVoxels + j] += v;
+                        // a run of equal keys starts where the previous lane's key differs
+                        // (wave_shr:1; lane 0 keeps -2, no key); segmented scan on DPP
+                        const int kp = __builtin_amdgcn_update_dpp(-2, key, 0x138, 0xf, 0xf, false);
+                        int f = kp != key ? 1 : 0;
+                        seg_scan_step<0x111, 0xf>(v, f);
+                        seg_scan_step<0x112, 0xf>(v, f);
+                        seg_scan_step<0x114, 0xf>(v, f);
+                        seg_scan_step<0x118, 0xf>(v, f);
+                        seg_scan_step<0x142, 0xa>(v, f);
+                        seg_scan_step<0x143, 0xc>(v, f);
+                        // the run's last lane adds it (wave_shl:1; lane 63 keeps -2)
+                        const int kn = __builtin_amdgcn_update_dpp(-2, key, 0x130, 0xf, 0xf, false);
+                        if (valid && kn != key) psi[(aa[h] - a0) * kPsiStride + wave * kWaveVoxels + j] += v;
                     }
                 }
             }
