@@ -33,8 +33,8 @@ sys.path.insert(0, ROOT)
 os.environ.setdefault("OMP_PROC_BIND", "close")
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-# what the path computes in: float32 data and sums; the dense products inside WC
-# take FP16 hi/lo operand pairs on the matrix cores with FP32 accumulation
+# what the path computes in: float32 data and sums; the dense projections inside WC
+# are exact integer sums of 8-bit digit products on the matrix cores, rounded once
 ARITHMETIC = "f32; WC projections exact int8-MFMA digit products of 30-bit fixed-point D and y, rounded once"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector; a plain v_fma_f32 loop reached 132 TFLOP/s here
 

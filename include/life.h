@@ -278,8 +278,10 @@ life_status life_plan_export(life_plan_t plan, int32_t *vox_ptr, int16_t *atom_v
  * form of the inner loop): y[t + N_theta*v] = sum over nonzeros c of voxel v of
  * D[t + N_theta*atom_c] * phi_c * w[fascicle_c].
  *   D (device, N_theta*N_a), w (device, N_f) are read; y (device, N_theta*N_v) is
- *   overwritten (voxels with no nonzero get 0).  Every nonzero is processed: a
- *   zero weight contributes an exact zero (no data-dependent branches).
+ *   overwritten (voxels with no nonzero get 0).  Nonzeros of a zero weight add
+ *   nothing (Sec. 2.2): in a 64-voxel chunk where at least 1/8 of the weights are
+ *   zero, their products are skipped (the sums of the others keep their order
+ *   and value); elsewhere they add an exact zero.
  * Errors: LIFE_EINVAL (NULL plan or pointer with a nonzero size), LIFE_EDEVICE. */
 life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y, void *stream);
 
@@ -289,9 +291,10 @@ life_status life_dsc(life_plan_t plan, const float *D, const float *w, float *y,
  *   D (device), y (device, N_theta*N_v) are read; g (device, N_f) is
  *   overwritten (fascicles with no nonzero get 0).
  * Precision: with N_theta <= 128 the inner products <D[:,a], y[:,v]> are formed
- *   on the matrix cores from FP16 hi/lo pairs of power-of-two scaled columns of D
- *   and y (about 22 significant bits per operand, FP32 accumulation; relative
- *   error per product about 3 * 2^-22 against 2^-24 for an FP32 FMA); the sums
+ *   on the matrix cores as exact integer sums of 8-bit digit products: each
+ *   column of D and of y is scaled by a power of two and rounded to a 30-bit
+ *   integer (to 2^-31 of its largest magnitude), the digit products of weight
+ *   2^16 and below are dropped, and the sum is rounded once to float; the sums
  *   over nonzeros are FP32 in a fixed order.  Larger N_theta uses FP32 FMAs.
  * Errors: as life_dsc. */
 life_status life_wc(life_plan_t plan, const float *D, const float *y, float *g, void *stream);

@@ -4,8 +4,9 @@
 //      over the voxel-sorted nonzeros; every y column is accumulated in
 //      registers and written exactly once (no atomics).
 // WC   g = M^T y  (the transpose product of eq. 6), in two deterministic passes:
-//      (1) voxel-major: each nonzero c gets z_c = phi_c <D[:,atom_c], y[:,v]>;
-//      (2) fascicle-major: g[f] = sum of z over the fascicle's nonzeros, read
+//      (1) voxel-major: each nonzero c gets z_c = phi_c <D[:,atom_c], y[:,v]>
+//          (the chunked path keeps one sum per run of a fascicle's nonzeros);
+//      (2) fascicle-major: g[f] = sum of those values over the fascicle, read
 //          through the fascicle-sorted permutation, in a fixed tree order.
 // SBB  one SBB-NNLS iteration (Algorithm 1) chains these with a mask kernel, a
 //      one-block step-length kernel and an update kernel; every scalar stays on
@@ -25,8 +26,9 @@
 //     wavefront with N_theta = 96 would idle lanes and read D through the cache
 //     hierarchy at 384 B per nonzero.
 //     WC pass 1 forms all the tile's projections of the chunk at once, as the
-//     dense block D_tile^T Y_chunk on the matrix cores (split-FP16 operands),
-//     then each nonzero is one lookup; its z values leave through an LDS stage.
+//     dense block D_tile^T Y_chunk on the matrix cores (exact 8-bit digit
+//     products), then each nonzero is one lookup, and a segmented scan leaves one
+//     value per run of a fascicle's nonzeros.
 //   generic (any n_theta <= 1024): 32 lanes per voxel, D read through L1/L2.
 #include <hip/hip_runtime.h>
 
@@ -273,22 +275,27 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         constexpr bool SKIP = decltype(skip_tag)::value;
         for (int t = 0; t < T; ++t) {
             const int a0 = t * TA;
+            // two-stage prefetch over batch starts: the scalars of batch i+2 and the
+            // w gather of batch i+1 are in flight while batch i is computed; the first
+            // two batches of a tile are requested before its staging
+            const WaveRange R(wave_work, chunk, t, T, wave);
+            const bool any = R.p[kWaveVoxels] != R.p[0];
+            int bq = R.next(R.p[0]);
+            uint2 r = make_uint2(0u, 0u), r1 = make_uint2(0u, 0u);
+            if (any) {
+                r = rec[R.entry(R.p[0], mypos)];
+                r1 = rec[R.entry(bq, mypos)];
+            }
             if (t > 0) {   // (tile 0 is staged above)
                 __syncthreads();
                 stage_tile<ROW>(lds, D, a0, min(na, a0 + TA) - a0, nth, vec);
                 __syncthreads();
             }
-            const WaveRange R(wave_work, chunk, t, T, wave);
-            if (R.p[kWaveVoxels] == R.p[0]) continue;   // nothing for this wave in this tile
-            // two-stage prefetch over batch starts: the scalars of batch i+2 and the
-            // w gather of batch i+1 are in flight while batch i is computed
-            int bq = R.next(R.p[0]);
-            int ix = R.entry(R.p[0], mypos);
-            uint2 r = rec[ix];
+            if (!any) continue;   // nothing for this wave in this tile
+            int ix;
             int a_0 = (int)(r.x & 0xffffu), f_0 = (int)(r.x >> 16);
             float ph_0 = __uint_as_float(r.y);
-            ix = R.entry(bq, mypos);
-            r = rec[ix];
+            r = r1;
             int a_1 = (int)(r.x & 0xffffu), f_1 = (int)(r.x >> 16);
             float ph_1 = __uint_as_float(r.y);
             float w_0 = wl[f_0];
@@ -540,53 +547,60 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
     }
 
     for (int t = 0; t < T; ++t) {
+        // this wave's bucket range; its first two batches of records are requested
+        // before P is formed (their latency hides behind the matrix-core phase)
+        const int wi = (chunk * T + t) * kChunkWaves + wave;
+        const int eb = uni(wc_wave[wi]), ee = uni(wc_wave[wi + 1]);
+        uint2 r0 = make_uint2(0u, 0u), r1 = make_uint2(0u, 0u);
+        if (eb < ee) {
+            r0 = wrec[eb + lane < ee ? eb + lane : ee - 1];
+            r1 = wrec[eb + 64 + lane < ee ? eb + 64 + lane : ee - 1];
+        }
         __syncthreads();   // Y is staged / the previous tile's lookups are done with P
-        if (wave < AB) {
-            // the A digits come from L2 once per slot half (held for both halves they
-            // would not fit the registers beside the accumulators)
-            const i32x4 *fa = frag + (size_t)(t * AB + wave) * KS * kDigits * 64 + lane;
-            const int col = lane & 31, kh = 16 * (lane >> 5);
-            const float *ds = dscale + (size_t)(t * AB + wave) * 32;
+        // units (32-atom block, 32-slot half) dealt round-robin to the 16 waves: the
+        // matrix cores bound this phase, so the units are spread over all four SIMDs
+        // (with one unit per block the busiest SIMD would run a third more of them)
 #pragma unroll 1
-            for (int h = 0; h < 2; ++h) {
-                i32x16 c6 = {}, c5 = {}, c4 = {}, c3 = {};
-                const int8_t *yb = Yq + (32 * h + col) * YS + kh;
-                for (int ks = 0; ks < KS; ++ks) {
-                    i32x4 a[kDigits];
+        for (int u = wave; u < 2 * AB; u += kChunkWaves) {
+            const int ab = u >> 1, h = u & 1;
+            const i32x4 *fa = frag + (size_t)(t * AB + ab) * KS * kDigits * 64 + lane;
+            const int col = lane & 31, kh = 16 * (lane >> 5);
+            const float *ds = dscale + (size_t)(t * AB + ab) * 32;
+            i32x16 c6 = {}, c5 = {}, c4 = {}, c3 = {};
+            const int8_t *yb = Yq + (32 * h + col) * YS + kh;
+            for (int ks = 0; ks < KS; ++ks) {
+                i32x4 a[kDigits];
 #pragma unroll
-                    for (int g = 0; g < kDigits; ++g) a[g] = fa[(ks * kDigits + g) * 64];
-                    // one B digit at a time (fewer live registers): digit j meets A digits
-                    // i >= 3 - j, and the product goes to the class of weight i + j
-                    const int8_t *yk = yb + 32 * ks;
-                    i32x4 b = *reinterpret_cast<const i32x4 *>(yk + 3 * kChunkVoxels * YS);
-                    c6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c6, 0, 0, 0);
-                    c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c5, 0, 0, 0);
-                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c4, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b, c3, 0, 0, 0);
-                    b = *reinterpret_cast<const i32x4 *>(yk + 2 * kChunkVoxels * YS);
-                    c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c5, 0, 0, 0);
-                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c4, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c3, 0, 0, 0);
-                    b = *reinterpret_cast<const i32x4 *>(yk + kChunkVoxels * YS);
-                    c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c4, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c3, 0, 0, 0);
-                    b = *reinterpret_cast<const i32x4 *>(yk);
-                    c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c3, 0, 0, 0);
-                }
-                // accumulator r of lane l holds (atom row 8 (r/4) + 4 (l/32) + r%4, slot 32 h + l%32)
-                const float sv = yscale[32 * h + col];
+                for (int g = 0; g < kDigits; ++g) a[g] = fa[(ks * kDigits + g) * 64];
+                // one B digit at a time (fewer live registers): digit j meets A digits
+                // i >= 3 - j, and the product goes to the class of weight i + j
+                const int8_t *yk = yb + 32 * ks;
+                i32x4 b = *reinterpret_cast<const i32x4 *>(yk + 3 * kChunkVoxels * YS);
+                c6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c6, 0, 0, 0);
+                c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c5, 0, 0, 0);
+                c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c4, 0, 0, 0);
+                c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b, c3, 0, 0, 0);
+                b = *reinterpret_cast<const i32x4 *>(yk + 2 * kChunkVoxels * YS);
+                c5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c5, 0, 0, 0);
+                c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c4, 0, 0, 0);
+                c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b, c3, 0, 0, 0);
+                b = *reinterpret_cast<const i32x4 *>(yk + kChunkVoxels * YS);
+                c4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c4, 0, 0, 0);
+                c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[2], b, c3, 0, 0, 0);
+                b = *reinterpret_cast<const i32x4 *>(yk);
+                c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[3], b, c3, 0, 0, 0);
+            }
+            // accumulator r of lane l holds (atom row 8 (r/4) + 4 (l/32) + r%4, slot 32 h + l%32)
+            const float sv = yscale[32 * h + col];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                    const double exact = (((double)c6[r] * 256.0 + (double)c5[r]) * 256.0 + (double)c4[r]) * 256.0 +
-                                         (double)c3[r];
-                    P[(32 * wave + row) * kPS + 32 * h + col] = ((float)exact * ds[row]) * sv;
-                }
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                const double exact = (((double)c6[r] * 256.0 + (double)c5[r]) * 256.0 + (double)c4[r]) * 256.0 +
+                                     (double)c3[r];
+                P[(32 * ab + row) * kPS + 32 * h + col] = ((float)exact * ds[row]) * sv;
             }
         }
         __syncthreads();
-        const int wi = (chunk * T + t) * kChunkWaves + wave;
-        const int eb = uni(wc_wave[wi]), ee = uni(wc_wave[wi + 1]);
         if (eb >= ee) continue;
         int run = uni(wc_wrun[wi]);      // index of the run open before the current batch, plus one
         float carry = 0.f;
@@ -597,7 +611,8 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = b0 + 64 * u + lane;
-                const uint2 r = wrec[e < ee ? e : ee - 1];
+                uint2 r = u == 0 ? r0 : r1;
+                if (u > 1 || b0 != eb) r = wrec[e < ee ? e : ee - 1];
                 kk[u] = e < ee ? (int)r.x : (int)life::kRunStart;
                 pp[u] = e < ee ? __uint_as_float(r.y) : 0.f;
             }
