@@ -18,8 +18,9 @@
 //     tiles of 265 atoms for N_theta = 96; a plan may be built with other tile
 //     sizes, and life_plan_autotune picks one by timing).
 //     DSC stages the tile in LDS; inside a wave, four 16-lane groups each take one
-//     nonzero per step, lane l of a group holding theta = 32c + 2l, 2l + 1, so a
-//     step is 3 ds_read_b64 + 6 FMA per lane.  The per-nonzero scalars are loaded
+//     nonzero per step, lane l of a group holding theta = 4l .. 4l + 3 and
+//     64 + 2l, 65 + 2l, so a step is one ds_read_b128 (the 16 lanes of a group
+//     read 256 contiguous bytes), one ds_read_b64 and 6 FMA per lane.  The per-nonzero scalars are loaded
 //     coalesced once per 64 nonzeros and broadcast inside each group with a DPP
 //     row broadcast (a VALU move, leaving the LDS pipe to the D reads).  This
 //     replaces the paper's one-warp-per-sub-vector mapping, which on a 64-wide
@@ -205,9 +206,10 @@ struct WaveRange {
     }
 };
 
-// Lane layout of the chunked kernels: a wave is kSE groups of kGL = 16 lanes; at
-// step k of a batch, group g handles entry kSE*k + g, and lane l of a group holds
-// theta = 32c + 2l + {0, 1} for c < NC (each LDS row read as NC float2 per lane).
+// Lane layout of the chunked DSC: a wave is kSE groups of kGL = 16 lanes; at step
+// k of a batch, group g handles entry kSE*k + g, and lane l of a group holds
+// theta = 64q + 4l + {0..3} for q < NC/2 (a float4 read per 64-float block of the
+// LDS row) and, for odd NC, theta = 64 (NC/2) + 2l + {0, 1} (a float2 read).
 // The lane that loads the scalars of entry kSE*k + g is lane kGL*g + k, so a row
 // broadcast of lane k hands every group its entry.  Batches never span two voxel
 // slots; full batches run 16 branch-free steps, the last batch of a slot is
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     float *lds = reinterpret_cast<float *>(lds4);
     constexpr int ROW = NC * 32;
     constexpr int PER = NC * 2;
+    constexpr int NQ = NC / 2, NR = NC % 2;   // 64-float blocks of a row (16-byte reads), 32-float tail
     const int chunk = chunk_map[blockIdx.x];   // -1: no chunk for this workgroup (uniform exit)
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -322,12 +325,19 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
                     // nonzero products moves them to its first steps)
 #define LIFE_DSC_STEP(K)                                                                  \
         {                                                                                     \
-            const int ak = bcast16<K>(aoff) + 2 * l16;                                        \
+            const int ak = bcast16<K>(aoff);                                                  \
             const float sk = bcast16f<K>(s);                                                  \
-            _Pragma("unroll") for (int cc = 0; cc < NC; ++cc) {                               \
-                const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 32 * cc);       \
-                acc[j][2 * cc + 0] = fmaf(d.x, sk, acc[j][2 * cc + 0]);                       \
-                acc[j][2 * cc + 1] = fmaf(d.y, sk, acc[j][2 * cc + 1]);                       \
+            _Pragma("unroll") for (int q = 0; q < NQ; ++q) {                                  \
+                const float4 d = *reinterpret_cast<const float4 *>(lds + ak + 4 * l16 + 64 * q); \
+                acc[j][4 * q + 0] = fmaf(d.x, sk, acc[j][4 * q + 0]);                         \
+                acc[j][4 * q + 1] = fmaf(d.y, sk, acc[j][4 * q + 1]);                         \
+                acc[j][4 * q + 2] = fmaf(d.z, sk, acc[j][4 * q + 2]);                         \
+                acc[j][4 * q + 3] = fmaf(d.w, sk, acc[j][4 * q + 3]);                         \
+            }                                                                                 \
+            if constexpr (NR) {                                                               \
+                const float2 d = *reinterpret_cast<const float2 *>(lds + ak + 2 * l16 + 64 * NQ); \
+                acc[j][4 * NQ + 0] = fmaf(d.x, sk, acc[j][4 * NQ + 0]);                       \
+                acc[j][4 * NQ + 1] = fmaf(d.y, sk, acc[j][4 * NQ + 1]);                       \
             }                                                                                 \
         }
                     int n = m;   // entries to cover (the rest carry zero products)
@@ -394,17 +404,15 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
             float *yv = y + (size_t)v * nth;
             const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int th = 32 * cc + 2 * l16 + q;
-                    if (th < nth) {
-                        float r = acc[j][2 * cc + q];
-                        if (bv) r -= bv[th];
-                        yv[th] = r;
-                        sq += (double)r * (double)r;
-                    }
+            for (int e = 0; e < PER; ++e) {
+                const int th = e < 4 * NQ ? 64 * (e / 4) + 4 * l16 + e % 4 : 64 * NQ + 2 * l16 + (e - 4 * NQ);
+                if (th < nth) {
+                    float r = acc[j][e];
+                    if (bv) r -= bv[th];
+                    yv[th] = r;
+                    sq += (double)r * (double)r;
                 }
+            }
         }
     }
     if (part) block_sum_store<kWG>(sq, part, chunk);
