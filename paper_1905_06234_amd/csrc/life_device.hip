@@ -256,6 +256,15 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
         for (int o = 32; o >= 1; o >>= 1) nz += __shfl_xor(nz, o, 64);
         if (lane == 0) zero_w[wave] = nz;
     }
+    // group g of the wave writes slot g at the end; its b values are requested now
+    const int g = lane / kGL, l16 = lane % kGL;
+    const int vme = chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + g];
+    float bme[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int th = e < 4 * NQ ? 64 * (e / 4) + 4 * l16 + e % 4 : 64 * NQ + 2 * l16 + (e - 4 * NQ);
+        bme[e] = bsub && vme >= 0 && th < nth ? bsub[(size_t)vme * nth + th] : 0.f;
+    }
     // the first tile (its LDS region is not the weights')
     stage_tile<ROW>(lds, D, 0, min(na, TA), nth, vec);
     __syncthreads();
@@ -266,7 +275,6 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
 #pragma unroll
     for (int i = 0; i < kChunkWaves; ++i) n_zero += zero_w[i];
     const bool skip = uni(8 * n_zero >= nl ? 1 : 0) != 0;
-    const int g = lane / kGL, l16 = lane % kGL;
     const int mypos = kSE * l16 + g;       // entry of a batch whose scalars this lane loads
     float acc[kWaveVoxels][PER];
 #pragma unroll
@@ -388,8 +396,10 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
     else
         tiles(std::false_type{});
 
-    // combine the group partials (fixed butterfly) and write each column once
+    // combine the group partials (fixed butterfly: every group gets the sums) and
+    // write each column once, group g writing slot g
     double sq = 0.0;
+    float mine[PER];
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
 #pragma unroll
@@ -397,21 +407,18 @@ __global__ __launch_bounds__(kWG) void k_dsc_chunk(const int32_t *__restrict__ c
             float x = acc[j][e];
             x += __shfl_xor(x, 16, 64);
             x += __shfl_xor(x, 32, 64);
-            acc[j][e] = x;
+            if (j == 0 || g == j) mine[e] = x;
         }
-        const int v = uni(chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + j]);
-        if (v >= 0 && g == 0) {
-            float *yv = y + (size_t)v * nth;
-            const float *bv = bsub ? bsub + (size_t)v * nth : nullptr;
+    }
+    if (vme >= 0) {
+        float *yv = y + (size_t)vme * nth;
 #pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const int th = e < 4 * NQ ? 64 * (e / 4) + 4 * l16 + e % 4 : 64 * NQ + 2 * l16 + (e - 4 * NQ);
-                if (th < nth) {
-                    float r = acc[j][e];
-                    if (bv) r -= bv[th];
-                    yv[th] = r;
-                    sq += (double)r * (double)r;
-                }
+        for (int e = 0; e < PER; ++e) {
+            const int th = e < 4 * NQ ? 64 * (e / 4) + 4 * l16 + e % 4 : 64 * NQ + 2 * l16 + (e - 4 * NQ);
+            if (th < nth) {
+                const float r = mine[e] - bme[e];
+                yv[th] = r;
+                sq += (double)r * (double)r;
             }
         }
     }
@@ -503,15 +510,16 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
 
 // WC pass 1: one value per run of one fascicle's nonzeros in one (chunk, tile):
 // zrun[r] = sum over the run's entries e of phi_e * <D[:, atom_e], y[:, v_e]>.
-// Per tile, waves 0..AB-1 first form P = D_tile^T Y_chunk in LDS (one 32-atom block
-// each, both 32-slot halves); then every wave walks its own entry range of the
-// (chunk, tile) bucket (cut at run starts) in batches of 64 consecutive entries,
-// four batches requested at once: each lane looks up its entry's projection in P, and a
-// segmented scan over the batch (Hillis-Steele with run-start flags, fixed order)
-// sums each run; the lane at a run's end writes it, a run that crosses into the
-// next batch carries its partial sum there.
-// LDS: P [32 AB][kPS] floats, Y hi and lo [64 slots][YS] halves (YS = 16 KS + 8:
-// conflict-free 16-byte reads along theta), the 64 slot scales.
+// Per tile, the waves first form P = D_tile^T Y_chunk in LDS (units of one 32-atom
+// block and one 32-slot half, dealt round-robin); then every wave walks its own
+// entry range of the (chunk, tile) bucket (cut at run starts) in batches of 64
+// consecutive entries, four batches requested at once: each lane looks up its
+// entry's projection in P, and a segmented scan over the batch (DPP row shifts and
+// row broadcasts with run-start flags, fixed order) sums each run; the lane at a
+// run's end writes it, a run that crosses into the next batch carries its partial
+// sum there.
+// LDS: P [32 AB][kPS] floats, the digits of Y [4 digits][64 slots][YS] bytes
+// (YS = 32 KS + kQ8Pad), the 64 slot scales.
 __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ chunk_map,
                                                   const int32_t *__restrict__ chunk_vox,
                                                   const uint2 *__restrict__ wrec,
@@ -532,16 +540,34 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
     if (chunk < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // the chunk's y columns, each scaled by its own power of two and cut into digits
+    // this wave's bucket range in a tile and its first two batches of records (for
+    // tile 0 requested before the y columns, for the others before P is formed)
+    int eb = 0, ee = 0;
+    uint2 r0 = make_uint2(0u, 0u), r1 = make_uint2(0u, 0u);
+    auto first_records = [&](int t) {
+        const int wi = (chunk * T + t) * kChunkWaves + wave;
+        eb = uni(wc_wave[wi]);
+        ee = uni(wc_wave[wi + 1]);
+        if (eb < ee) {
+            r0 = wrec[eb + lane < ee ? eb + lane : ee - 1];
+            r1 = wrec[eb + 64 + lane < ee ? eb + 64 + lane : ee - 1];
+        }
+    };
+    first_records(0);
+
+    // the chunk's y columns (all requested at once), each scaled by its own power of
+    // two and cut into digits
+    float xs0[kWaveVoxels], xs1[kWaveVoxels];
+#pragma unroll
+    for (int j = 0; j < kWaveVoxels; ++j) {
+        const int v = uni(chunk_vox[chunk * kChunkVoxels + wave * kWaveVoxels + j]);
+        xs0[j] = v >= 0 && lane < nth ? y[(size_t)v * nth + lane] : 0.f;
+        xs1[j] = v >= 0 && lane + 64 < nth ? y[(size_t)v * nth + lane + 64] : 0.f;
+    }
 #pragma unroll
     for (int j = 0; j < kWaveVoxels; ++j) {
         const int slot = wave * kWaveVoxels + j;
-        const int v = uni(chunk_vox[chunk * kChunkVoxels + slot]);
-        float x0 = 0.f, x1 = 0.f;
-        if (v >= 0) {
-            if (lane < nth) x0 = y[(size_t)v * nth + lane];
-            if (lane + 64 < nth) x1 = y[(size_t)v * nth + lane + 64];
-        }
+        const float x0 = xs0[j], x1 = xs1[j];
         float m = fmaxf(fabsf(x0), fabsf(x1));
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
@@ -555,15 +581,7 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
     }
 
     for (int t = 0; t < T; ++t) {
-        // this wave's bucket range; its first two batches of records are requested
-        // before P is formed (their latency hides behind the matrix-core phase)
-        const int wi = (chunk * T + t) * kChunkWaves + wave;
-        const int eb = uni(wc_wave[wi]), ee = uni(wc_wave[wi + 1]);
-        uint2 r0 = make_uint2(0u, 0u), r1 = make_uint2(0u, 0u);
-        if (eb < ee) {
-            r0 = wrec[eb + lane < ee ? eb + lane : ee - 1];
-            r1 = wrec[eb + 64 + lane < ee ? eb + 64 + lane : ee - 1];
-        }
+        if (t > 0) first_records(t);   // (their latency hides behind the matrix-core phase)
         __syncthreads();   // Y is staged / the previous tile's lookups are done with P
         // units (32-atom block, 32-slot half) dealt round-robin to the 16 waves: the
         // matrix cores bound this phase, so the units are spread over all four SIMDs
@@ -610,7 +628,7 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
         }
         __syncthreads();
         if (eb >= ee) continue;
-        int run = uni(wc_wrun[wi]);      // index of the run open before the current batch, plus one
+        int run = uni(wc_wrun[(chunk * T + t) * kChunkWaves + wave]);      // index of the run open before the current batch, plus one
         float carry = 0.f;
         for (int b0 = eb; b0 < ee; b0 += 4 * 64) {
             // four batches of keys and values requested at once, and the key after them
