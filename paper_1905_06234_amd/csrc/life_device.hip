@@ -520,6 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_split_dt(const float *__restrict__ D
 // sum there.
 // LDS: P [32 AB][kPS] floats, the digits of Y [4 digits][64 slots][YS] bytes
 // (YS = 32 KS + kQ8Pad), the 64 slot scales.
+template <int KS>
 __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ chunk_map,
                                                   const int32_t *__restrict__ chunk_vox,
                                                   const uint2 *__restrict__ wrec,
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
                                                   const i32x4 *__restrict__ frag,
                                                   const float *__restrict__ dscale,
                                                   const float *__restrict__ y,
-                                                  float *__restrict__ zrun, int nth, int T, int AB, int KS, Gate gate)
+                                                  float *__restrict__ zrun, int nth, int T, int AB, Gate gate)
 {
     if (gated_off(gate)) return;   // uniform over the grid
     extern __shared__ float4 lds4[];
@@ -1485,7 +1486,8 @@ hipError_t allow_lds()
 {
     const int bytes = life::kLdsBudget;
     const void *fns[] = {(const void *)k_dsc_chunk<1>, (const void *)k_dsc_chunk<2>, (const void *)k_dsc_chunk<3>,
-                         (const void *)k_dsc_chunk<4>, (const void *)k_wcr_mfma, (const void *)k_dd_chunk<1>,
+                         (const void *)k_dsc_chunk<4>, (const void *)k_wcr_mfma<1>, (const void *)k_wcr_mfma<2>,
+                         (const void *)k_wcr_mfma<3>, (const void *)k_wcr_mfma<4>, (const void *)k_dd_chunk<1>,
                          (const void *)k_dd_chunk<2>, (const void *)k_dd_chunk<3>, (const void *)k_dd_chunk<5>,
                          (const void *)k_dd_chunk<9>, (const void *)k_dd_chunk<12>};
     for (const void *f : fns) {
@@ -1538,9 +1540,18 @@ life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, cons
                     k_split_dt<<<cdiv((int64_t)T * AB * 32, kBlock / 64), kBlock, 0, s>>>(D, ws.dt_frag, ws.dt_scale,
                                                                                          nth, p->dims.n_atoms, T, TA,
                                                                                          AB, KS, gate);
-                k_wcr_mfma<<<p->chunk_grid, kWG, p->wcr_lds, s>>>(p->chunk_map, p->chunk_vox, p->wc_rec,
-                                                                  p->wc_wave, p->wc_wrun, ws.dt_frag, ws.dt_scale, y,
-                                                                  ws.z, nth, T, AB, KS, gate);
+#define LIFE_WCR(K)                                                                                        \
+    k_wcr_mfma<K><<<p->chunk_grid, kWG, p->wcr_lds, s>>>(p->chunk_map, p->chunk_vox, p->wc_rec, p->wc_wave,     \
+                                                         p->wc_wrun, ws.dt_frag, ws.dt_scale, y, ws.z, nth, T, AB, gate)
+                // the k-steps as a compile-time count: the A digits of the next k-step
+                // can then be requested while the matrix cores work on this one
+                switch (KS) {   // N_theta <= 128
+                case 1: LIFE_WCR(1); break;
+                case 2: LIFE_WCR(2); break;
+                case 3: LIFE_WCR(3); break;
+                default: LIFE_WCR(4); break;
+                }
+#undef LIFE_WCR
             });
         } else {
             const int grid = cdiv(nv, kSegPerBlock);
