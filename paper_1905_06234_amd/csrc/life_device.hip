@@ -622,8 +622,10 @@ __global__ __launch_bounds__(kWG) void k_wcr_mfma(const int32_t *__restrict__ ch
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                const double exact = (((double)c6[r] * 256.0 + (double)c5[r]) * 256.0 + (double)c4[r]) * 256.0 +
-                                     (double)c3[r];
+                // |C6| <= 2^19, |C5| <= 2^21, |C4| <= 2^22, |C3| < 2^22.6 for K <= 128, so both
+                // halves are exact in 32-bit integers and their combination in double
+                const int hi = c6[r] * 256 + c5[r], lo = c4[r] * 256 + c3[r];
+                const double exact = fma((double)hi, 65536.0, (double)lo);
                 P[(32 * ab + row) * kPS + 32 * h + col] = ((float)exact * ds[row]) * sv;
             }
         }
