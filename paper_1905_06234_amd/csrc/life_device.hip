@@ -74,7 +74,8 @@ constexpr int kBlock = 256;                  // threads per block of the generic
 constexpr int kSeg = 32;                     // lanes per voxel segment (generic kernels)
 constexpr int kSegPerBlock = kBlock / kSeg;  // voxels per block (generic kernels)
 constexpr int kFasLanes = 16;                // lanes per fascicle in the WC sum
-constexpr int kFasPerBlock = kBlock / kFasLanes;
+constexpr int kSumBlock = 512;               // threads per block of the WC sum (measured best)
+constexpr int kFasPerBlock = kSumBlock / kFasLanes;
 constexpr int kWG = kChunkWaves * 64;        // threads per chunk workgroup
 constexpr int kAlphaThreads = 1024;
 
@@ -786,12 +787,12 @@ __global__ __launch_bounds__(kBlock) void k_wc_z(const int32_t *__restrict__ vpt
 // WC pass 2: g[out(r)] = sum_{j in seg(r)} z[wperm[j]] for the fascicle of rank r
 // (16 lanes per fascicle; each lane keeps 4 index loads and 4 gathers in flight;
 // fixed summation tree); out(r) = gmap[r] (caller order) or r.
-__global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
-                                                    const int32_t *__restrict__ wperm,
-                                                    const float *__restrict__ z,
-                                                    const int32_t *__restrict__ gmap,
-                                                    float *__restrict__ g, double *__restrict__ part,
-                                                    int nf, Gate gate)
+__global__ __launch_bounds__(kSumBlock) void k_wc_sum(const int32_t *__restrict__ fptr,
+                                                       const int32_t *__restrict__ wperm,
+                                                       const float *__restrict__ z,
+                                                       const int32_t *__restrict__ gmap,
+                                                       float *__restrict__ g, double *__restrict__ part,
+                                                       int nf, Gate gate)
 {
     if (gated_off(gate)) return;   // uniform over the grid
     const int lane = threadIdx.x & (kFasLanes - 1);
@@ -819,7 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_wc_sum(const int32_t *__restrict__ f
         g[gmap ? gmap[f] : f] = s;
         sq = (double)s * (double)s;
     }
-    if (part) block_sum_store<kBlock>(sq, part, blockIdx.x);
+    if (part) block_sum_store<kSumBlock>(sq, part, blockIdx.x);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -1567,9 +1568,8 @@ life_status enqueue_wc(life_plan_s *p, const Workspace &ws, const float *D, cons
     if (nf > 0) {
         const int grid = cdiv(nf, kFasPerBlock);
         st = launch(p, gate.st ? LIFE_K_WC_SUM_2ND : LIFE_K_WC_SUM, s, [&] {
-            k_wc_sum<<<grid, kBlock, 0, s>>>(chunked(p) ? p->rr_ptr : p->fas_ptr, chunked(p) ? p->rr : p->wc_perm,
-                                             ws.z, gmap, g,
-                                             part, nf, gate);
+            k_wc_sum<<<grid, kSumBlock, 0, s>>>(chunked(p) ? p->rr_ptr : p->fas_ptr,
+                                                chunked(p) ? p->rr : p->wc_perm, ws.z, gmap, g, part, nf, gate);
         });
     }
     return st;
